@@ -1,0 +1,184 @@
+/*
+ * qg.h -- C ABI of the MI355X state-vector circuit simulator (libqg.so).
+ *
+ * The library simulates the method of Q-GEAR (arXiv 2504.03967): a circuit given
+ * as gate-list tensors (Sec. 2.1 "Circuit encoding", App. B) is applied to a
+ * 2^n-amplitude complex state (App. A, eq. (hilbert)), which is then reduced to
+ * probabilities, seeded shot samples and Pauli-Z-string expectation values
+ * (the "circuit in, state and counts out" statement of Sec. 2 and App. A).
+ *
+ * Conventions shared by every entry point:
+ *  - Qubit q is bit q of the amplitude index (little-endian).  App. A's
+ *    3-qubit CX example (control q0, target q2 exchanges |100>,|101> and
+ *    |110>,|111>) is indices 1<->5 and 3<->7 under this reading.
+ *  - Amplitudes are interleaved complex: {re, im} pairs of double (QG_C128,
+ *    16 bytes) or float (QG_C64, 8 bytes), index-contiguous in device memory.
+ *  - Every call returns a qg_status (0 = success, < 0 = error) and never
+ *    throws.  On error, qg_last_error() returns a message for the calling
+ *    thread.  Arguments are validated on the host before anything is launched:
+ *    a failed validation leaves the state and all outputs untouched.
+ *  - Host arrays passed in (gate tensors, index lists, masks, coefficients)
+ *    are read before the call returns; the caller keeps ownership.
+ *  - Output pointers are device pointers owned by the caller.  Work is
+ *    enqueued on the HIP stream given to the call (or bound to the state) and
+ *    is asynchronous: outputs are valid after that stream has been
+ *    synchronised.  A kernel fault surfaces as QG_EDEVICE on a later call.
+ *  - A qg_state handle may be used from one thread at a time.
+ */
+#ifndef QGEAR_MI355X_QG_H_
+#define QGEAR_MI355X_QG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QG_OK = 0,
+    QG_EINVAL = -1,       /* an argument failed validation */
+    QG_ENOMEM = -2,       /* a device or host allocation failed, or the state does not fit */
+    QG_EDEVICE = -3,      /* a HIP runtime call or kernel launch failed */
+    QG_EUNSUPPORTED = -4, /* valid request the library does not implement */
+    QG_EINTERNAL = -5
+} qg_status;
+
+typedef enum { QG_C64 = 0, QG_C128 = 1 } qg_dtype;
+
+/* Gate codes of the circuit encoding.  Matrices act on (alpha_{bit=0}, alpha_{bit=1})
+ * of the target; c = cos(theta/2), s = sin(theta/2):
+ *   H = [[1,1],[1,-1]]/sqrt2        X = [[0,1],[1,0]]
+ *   RX = [[c,-is],[-is,c]]          RY = [[c,-s],[s,c]]
+ *   RZ = diag(e^{-i theta/2}, e^{+i theta/2})
+ *   U3(theta,phi,lambda) = [[c, -e^{i lambda} s], [e^{i phi} s, e^{i(phi+lambda)} c]]
+ *   CX: X on q1 where bit q0 = 1 (App. A, eq. (cx))
+ *   CZ: -1 where bits q0 and q1 are both 1
+ *   CP(theta): e^{i theta} where bits q0 and q1 are both 1 (the CR1 of eq. (cr1))
+ *   SWAP: exchange bits q0 and q1 */
+typedef enum {
+    QG_H = 0, QG_X = 1, QG_RX = 2, QG_RY = 3, QG_RZ = 4, QG_U3 = 5,
+    QG_CX = 6, QG_CZ = 7, QG_CP = 8, QG_SWAP = 9
+} qg_op;
+
+/* Fusion modes of qg_apply_circuit. */
+typedef enum {
+    QG_FUSE_NONE = 0,    /* one device pass per gate */
+    QG_FUSE_GREEDY = 1,  /* greedy fixed-width fusion: a pass holds consecutive gates whose
+                            non-diagonal targets span at most 5 qubits outside the low,
+                            always-resident tile qubits (the paper's gate fusion = 5, App. D.2) */
+    QG_FUSE_LEARNED = 2  /* cost-model planner (qg_mlp_*); falls back to greedy without a model */
+} qg_fusion;
+
+typedef struct qg_state qg_state; /* opaque */
+
+/* One circuit in the encoding of Sec. 2.1 / App. B, padded as in Lemma 2:
+ *   gate_type  [n_gates][3] = {code, q0, q1}: q0 = control or first qubit
+ *              (-1 for single-qubit gates), q1 = target or second qubit;
+ *   gate_param [n_gates][3] = {theta, phi, lambda}; single-parameter gates
+ *              (RX, RY, RZ, CP) read theta only; unused entries are ignored;
+ *   param_idx  [n_gates] trainable-parameter slot of the gate's theta, or -1;
+ *              may be NULL (no trainable parameters).  Only RX, RY, RZ and CP
+ *              may carry a slot. */
+typedef struct {
+    int32_t n_qubits;
+    int32_t n_gates;
+    const int32_t *gate_type;
+    const double *gate_param;
+    const int32_t *param_idx;
+} qg_circuit;
+
+/* Create a state of n_qubits qubits set to |0...0> (App. A, eq. (hilbert)).
+ * dev_buf: NULL -> the library allocates (and later frees) 2^n amplitudes;
+ * otherwise a caller-owned device buffer of at least buf_bytes >= 2^n * size
+ * of an amplitude, borrowed for the handle's lifetime and never freed.
+ * hip_stream: the hipStream_t (NULL = default stream) all work on this state
+ * is enqueued on.  Limits: 1 <= n <= 33 (QG_C128) or 34 (QG_C64).
+ * Errors: QG_EINVAL (n out of range, buffer too small, out NULL), QG_ENOMEM. */
+qg_status qg_state_alloc(int n_qubits, qg_dtype dtype, void *dev_buf, size_t buf_bytes,
+                         void *hip_stream, qg_state **out);
+
+/* Release a handle (and the buffer, if the library allocated it).  Waits for
+ * the state's stream.  NULL is accepted. */
+qg_status qg_state_free(qg_state *s);
+
+/* Reset the state to |0...0>. */
+qg_status qg_state_reset(qg_state *s);
+
+/* Re-bind the stream later calls on this state are enqueued on. */
+qg_status qg_state_set_stream(qg_state *s, void *hip_stream);
+
+/* Device pointer of the amplitudes, qubit count and dtype of a state. */
+qg_status qg_state_info(const qg_state *s, void **dev_ptr, int *n_qubits, qg_dtype *dtype);
+
+/* Apply the circuit's gates, in order, to the state (App. A: each gate is the
+ * Kronecker-product operator of eq. (tp) / eq. (cx) / eq. (cr1) applied to the
+ * whole vector).  The circuit must have the state's qubit count.
+ * fusion_mode: a qg_fusion value.  Results agree with gate-by-gate
+ * application up to floating-point rounding for every mode.
+ * Errors: QG_EINVAL (qubit out of range, q0 == q1 on a two-qubit gate, unknown
+ * code, non-finite parameter, n mismatch), QG_ENOMEM, QG_EDEVICE. */
+qg_status qg_apply_circuit(qg_state *s, const qg_circuit *c, int fusion_mode);
+
+/* Probabilities p_i = |alpha_i|^2 (eq. (hilbert)), computed in FP64 for both
+ * dtypes.  idx == NULL: all 2^n values into out[2^n]; otherwise n_idx host
+ * indices (each < 2^n) and out[n_idx].  out is a device pointer. */
+qg_status qg_probs(qg_state *s, const uint64_t *idx, int64_t n_idx, double *out);
+
+/* Draw `shots` samples of the basis-state index from p (the paper's "shots",
+ * Sec. 3 / Table 1).  Shot k uses the uniform u_k = (x >> 11) 2^-53 of the
+ * Philox4x32-10 block x = out1:out0 with key (seed lo, seed hi) and counter
+ * (k lo, k hi, 0, 0), and returns the smallest index i whose cumulative
+ * probability exceeds u_k * sum(p) (the GPU groups the cumulative sums in a
+ * 64-ary tree, so an r within rounding of a boundary may pick the neighbour).
+ * out_idx: device array of `shots` uint64, in shot order.  shots >= 0. */
+qg_status qg_sample(qg_state *s, int64_t shots, uint64_t seed, uint64_t *out_idx);
+
+/* Pauli-Z-string expectations <Z_m> = sum_i p_i (-1)^{popcount(i & zmask[m])}
+ * for n_terms host masks (each < 2^n), accumulated in FP64.  out_terms: device
+ * [n_terms] or NULL; out_sum: device scalar sum_m coeff[m] <Z_m> or NULL
+ * (coeff may be NULL only when out_sum is NULL).  n_terms >= 0. */
+qg_status qg_expval(qg_state *s, const uint64_t *zmask, const double *coeff, int n_terms,
+                    double *out_terms, double *out_sum);
+
+/* Value and gradient of f = sum_m coeff[m] <Z_{zmask[m]}> for the circuit applied
+ * to |0...0>, by one adjoint reverse sweep (Jones & Gacon 2020; the paper's
+ * "adjoint GPU modes", Sec. 2): for each gate with param_idx >= 0, RX/RY/RZ add
+ * Im<lambda|P|psi> and CP adds -2 Im<lambda|P11|psi> to grad[param_idx].
+ * The library allocates the two working states and releases them before
+ * returning.  out_value: device scalar; out_grad: device [n_params].
+ * Errors: QG_EINVAL (also for a slot >= n_params or on a gate that is not RX,
+ * RY, RZ or CP), QG_ENOMEM (two states do not fit). */
+qg_status qg_adjoint_grad(const qg_circuit *c, qg_dtype dtype, const uint64_t *zmask,
+                          const double *coeff, int n_terms, int n_params, void *hip_stream,
+                          double *out_value, double *out_grad);
+
+/* Batched form (the paper's parallel / multi-circuit mode, Sec. 2.4): n_circ
+ * independent circuits of possibly different qubit counts, all from |0...0>,
+ * run by one persistent launch; out[c] = sum_{i<n_c-1} <Z_i Z_{i+1}> of
+ * circuit c (obs_kind QG_OBS_ZZ_CHAIN), or sum over its CSR terms
+ * obs_off[c]..obs_off[c+1] of coeff * <Z_zmask> (QG_OBS_CSR).
+ * out: device [n_circ].  Circuits of up to 20 qubits. */
+typedef enum { QG_OBS_ZZ_CHAIN = 0, QG_OBS_CSR = 1 } qg_obs_kind;
+qg_status qg_batch_expval(const qg_circuit *circs, int n_circ, qg_dtype dtype, int obs_kind,
+                          const int64_t *obs_off, const uint64_t *zmask, const double *coeff,
+                          void *hip_stream, double *out);
+
+/* Plan inspection (host only, no device needed): the pass each gate of the
+ * circuit is executed in under fusion_mode, written to pass_of_gate[n_gates]
+ * (host, may be NULL), and the pass count to *n_passes.  Passes run in
+ * increasing order and cover every gate exactly once, in order. */
+qg_status qg_plan_passes(const qg_circuit *c, qg_dtype dtype, int fusion_mode,
+                         int32_t *pass_of_gate, int32_t *n_passes);
+
+/* Message describing the calling thread's last failed call ("" if none). */
+const char *qg_last_error(void);
+
+/* Library version string. */
+const char *qg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QGEAR_MI355X_QG_H_ */

@@ -1,0 +1,65 @@
+// qg_internal.h -- device program format shared by the host planner and the kernels.
+//
+// A circuit is executed as a sequence of passes.  A pass streams every "tile"
+// of the state through registers once: a tile is the set of 2^b amplitudes
+// whose indices agree on all qubits outside the pass's b tile qubits.  Inside
+// a tile each thread holds 2^rb amplitudes (rb "register" tile positions) and
+// the 2^tb threads of the workgroup cover the other tile positions.  Ops that
+// mix amplitudes (dense 2x2, controlled 2x2) need their target as a register
+// position; phases re-map which tile positions are register positions by an
+// exchange through LDS.  Diagonal ops and controls read index bits directly,
+// so they need no particular position and may even act on qubits outside the
+// tile (whose bits are constant over a tile).
+#pragma once
+#include <stdint.h>
+
+namespace qg {
+
+constexpr int kMaxTileBits = 14;
+constexpr int kMaxRegBits = 5;
+constexpr int kMaxThreadBits = 8;
+constexpr int kMaxRuns = 20;
+
+enum OpKind : int32_t {
+    OP_MAT = 0,    // dense 2x2 on register slot a: m = {m00, m01, m10, m11} (re, im)
+    OP_CMAT = 1,   // 2x2 on register slot a where the bit of qubit-ref c is 1
+    OP_DIAG1 = 2,  // amplitude *= (bit of ref a ? {m[2],m[3]} : {m[0],m[1]})
+    OP_DIAG2 = 3,  // amplitude *= {m[0], m[1]} where bits of refs a and c are both 1
+    OP_GRADX = 4,  // adjoint partial: Im<lam|X_a|psi>, a = register slot, into grad row g
+    OP_GRADY = 5,  // adjoint partial: Im<lam|Y_a|psi>
+    OP_GRADZ = 6,  // adjoint partial: Im<lam|Z_a|psi>, a = qubit-ref
+    OP_GRADP11 = 7 // adjoint partial: -2 Im<lam|P11(a,c)|psi>, a, c = qubit-refs
+};
+
+// Qubit reference: r >= 0 is a tile position; r < 0 is global qubit (-1 - r), outside the tile.
+constexpr int qref_global(int q) { return -1 - q; }
+
+struct DevOp {
+    int32_t kind;
+    int32_t a;
+    int32_t c;
+    int32_t g;      // gradient row for OP_GRAD*
+    double m[8];
+};
+
+struct PhaseDesc {
+    uint64_t thr_goff[kMaxThreadBits];  // global index offset of thread bit k
+    uint64_t reg_goff[kMaxRegBits];     // global index offset of register bit j
+    uint32_t thr_poff[kMaxThreadBits];  // tile position offset of thread bit k
+    uint32_t reg_poff[kMaxRegBits];     // tile position offset of register bit j
+    int32_t op_begin, op_end;
+    int32_t pad;
+};
+
+struct PassDesc {
+    int32_t b, rb, tb, n_runs;
+    int32_t run_start[kMaxRuns];   // runs of consecutive free (non-tile, non-fixed) qubits
+    int32_t run_len[kMaxRuns];
+    uint64_t fixed_mask, fixed_val;  // only tiles with (index & fixed_mask) == fixed_val are active
+    int32_t phase_begin, n_phase;
+    int32_t grad_base;   // first gradient row written by this pass (adjoint sweeps)
+    int32_t n_grad;      // gradient rows written by this pass
+    uint64_t n_tiles;    // active tiles = launch size
+};
+
+}  // namespace qg

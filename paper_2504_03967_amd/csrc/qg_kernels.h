@@ -1,0 +1,51 @@
+// qg_kernels.h -- host launchers of the gfx950 kernels (HIP runtime types only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qg_internal.h"
+
+namespace qg {
+
+// One pass of the tile kernel.  `dev` holds PassDesc[], PhaseDesc[] and DevOp[]
+// at the given byte offsets; `host_pass` is the same pass on the host (launch
+// shape).  ns = 1 (psi only) or 2 (psi and lam, adjoint sweep with gradient
+// partials gpart[row * gstride + tile * waves + wave]).
+hipError_t launch_tile(bool c64, const PassDesc &host_pass, const void *dev, size_t pass_off,
+                       size_t phase_off, size_t op_off, int pass_idx, int ns, void *psi,
+                       void *lam, double *gpart, int64_t gstride, hipStream_t st);
+
+// psi <- |0...0>
+hipError_t launch_zero_state(bool c64, void *psi, uint64_t dim, hipStream_t st);
+
+// out[i] = |psi_i|^2 (idx == NULL) or out[k] = |psi_{idx[k]}|^2.
+hipError_t launch_probs(bool c64, const void *psi, uint64_t dim, const uint64_t *idx, int64_t n,
+                        double *out, hipStream_t st);
+
+// Z-string expectations.  part: scratch of expval_partials(dim, n_terms) doubles.
+int64_t expval_partials(uint64_t dim, int n_terms);
+hipError_t launch_expval(bool c64, const void *psi, uint64_t dim, const uint64_t *masks,
+                         const double *coeff, int n_terms, double *part, double *out_terms,
+                         double *out_sum, hipStream_t st);
+
+// Shot sampling over a 64-ary tree of probability sums.  tree: scratch of
+// sample_tree_doubles(dim) doubles.
+int64_t sample_tree_doubles(uint64_t dim);
+hipError_t launch_sample(bool c64, const void *psi, uint64_t dim, int64_t shots, uint64_t seed,
+                         double *tree, uint64_t *out, hipStream_t st);
+
+// Adjoint helpers.
+// lam_i = (sum_m coeff_m (-1)^{popcount(i & mask_m)}) psi_i
+hipError_t launch_apply_observable(bool c64, const void *psi, void *lam, uint64_t dim,
+                                   const uint64_t *masks, const double *coeff, int n_terms,
+                                   hipStream_t st);
+// rows[r] = sum_{k < count} gpart[r * gstride + k] for r in [0, n_rows)
+hipError_t launch_grad_rows(const double *gpart, int64_t gstride, int64_t count, int n_rows,
+                            double *rows, hipStream_t st);
+// grad[s] = sum of rows[r] over r with row_slot[r] == s (in row order)
+hipError_t launch_grad_slots(const double *rows, const int32_t *row_slot, int n_rows, double *grad,
+                             int n_params, hipStream_t st);
+
+hipError_t set_kernel_attributes();
+
+}  // namespace qg

@@ -1,0 +1,420 @@
+// qg_plan.cpp -- validation, greedy fusion and tile/phase planning (host only).
+//
+// Every gate of the circuit becomes one or more ops of a pass (App. A gives the
+// operators; the textbook matrices are listed in qg.h).  A pass is executed by
+// the tile kernel: all tiles of the state are streamed once through registers,
+// so a pass costs one read and one write of the (active part of the) state
+// whatever the number of ops it holds.  That is the role the paper's backend
+// gives to gate fusion (fusion width 5, App. D.2), carried out here without
+// forming dense 2^k matrices.
+#include "qg_plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace qg {
+
+namespace {
+
+inline int popcount64(uint64_t x) { return __builtin_popcountll(x); }
+
+struct Item {
+    int kind;
+    int qa, qc;
+    double m[8];
+    int g;
+};
+
+bool is_one_qubit(int op) { return op >= QG_H && op <= QG_U3; }
+bool is_two_qubit(int op) { return op >= QG_CX && op <= QG_SWAP; }
+
+void put(double *m, int k, cd v) {
+    m[2 * k] = v.real();
+    m[2 * k + 1] = v.imag();
+}
+
+// Ops of one gate; `dagger` emits U^dagger.  In reverse sweeps a gradient op
+// (taken at the state right after the gate) precedes the daggered gate.
+void gate_items(const Gate &g, bool dagger, int grad_row, std::vector<Item> *out) {
+    Item it{};
+    it.g = -1;
+    if (grad_row >= 0) {
+        Item gi{};
+        gi.g = grad_row;
+        gi.qa = g.q1;
+        gi.qc = g.q0;
+        switch (g.op) {
+        case QG_RX: gi.kind = OP_GRADX; break;
+        case QG_RY: gi.kind = OP_GRADY; break;
+        case QG_RZ: gi.kind = OP_GRADZ; break;
+        case QG_CP: gi.kind = OP_GRADP11; break;
+        }
+        out->push_back(gi);
+    }
+    if (is_one_qubit(g.op) && g.op != QG_RZ) {
+        cd m[2][2];
+        gate_matrix(g.op, g.p, m);
+        if (dagger) {
+            cd d[2][2] = {{std::conj(m[0][0]), std::conj(m[1][0])}, {std::conj(m[0][1]), std::conj(m[1][1])}};
+            std::memcpy(m, d, sizeof d);
+        }
+        it.kind = OP_MAT;
+        it.qa = g.q1;
+        put(it.m, 0, m[0][0]);
+        put(it.m, 1, m[0][1]);
+        put(it.m, 2, m[1][0]);
+        put(it.m, 3, m[1][1]);
+        out->push_back(it);
+        return;
+    }
+    const double sgn = dagger ? -1.0 : 1.0;
+    switch (g.op) {
+    case QG_RZ:
+        it.kind = OP_DIAG1;
+        it.qa = g.q1;
+        put(it.m, 0, std::polar(1.0, -0.5 * sgn * g.p[0]));
+        put(it.m, 1, std::polar(1.0, 0.5 * sgn * g.p[0]));
+        out->push_back(it);
+        return;
+    case QG_CX:
+        it.kind = OP_CMAT;
+        it.qc = g.q0;
+        it.qa = g.q1;
+        put(it.m, 1, 1.0);
+        put(it.m, 2, 1.0);
+        out->push_back(it);
+        return;
+    case QG_CZ:
+    case QG_CP:
+        it.kind = OP_DIAG2;
+        it.qa = g.q0;
+        it.qc = g.q1;
+        put(it.m, 0, g.op == QG_CZ ? cd(-1.0, 0.0) : std::polar(1.0, sgn * g.p[0]));
+        out->push_back(it);
+        return;
+    case QG_SWAP: {
+        // SWAP(a, b) = CX(a->b) CX(b->a) CX(a->b)
+        int a = g.q0, b = g.q1;
+        int seq[3][2] = {{a, b}, {b, a}, {a, b}};
+        for (auto &s : seq) {
+            Item x{};
+            x.kind = OP_CMAT;
+            x.g = -1;
+            x.qc = s[0];
+            x.qa = s[1];
+            put(x.m, 1, 1.0);
+            put(x.m, 2, 1.0);
+            out->push_back(x);
+        }
+        return;
+    }
+    }
+}
+
+int needs_register(const Item &it) {
+    switch (it.kind) {
+    case OP_MAT:
+    case OP_CMAT:
+    case OP_GRADX:
+    case OP_GRADY:
+        return it.qa;
+    }
+    return -1;
+}
+
+}  // namespace
+
+PlanConfig default_config(int n, bool c64, int fusion) {
+    PlanConfig c;
+    c.n = n;
+    c.c64 = c64;
+    c.fusion = fusion;
+    if (c64) {
+        c.tile_bits = 13;
+        c.reg_bits = 5;
+        c.low_bits = 8;
+        c.max_high = 5;
+    } else {
+        c.tile_bits = 12;
+        c.reg_bits = 4;
+        c.low_bits = 7;
+        c.max_high = 5;
+    }
+    return c;
+}
+
+void gate_matrix(int op, const double *p, cd m[2][2]) {
+    const double c = std::cos(0.5 * p[0]), s = std::sin(0.5 * p[0]);
+    const cd I(0.0, 1.0);
+    switch (op) {
+    case QG_H: {
+        const double r = 1.0 / std::sqrt(2.0);
+        m[0][0] = r; m[0][1] = r; m[1][0] = r; m[1][1] = -r;
+        return;
+    }
+    case QG_X:
+        m[0][0] = 0.0; m[0][1] = 1.0; m[1][0] = 1.0; m[1][1] = 0.0;
+        return;
+    case QG_RX:
+        m[0][0] = c; m[0][1] = -I * s; m[1][0] = -I * s; m[1][1] = c;
+        return;
+    case QG_RY:
+        m[0][0] = c; m[0][1] = -s; m[1][0] = s; m[1][1] = c;
+        return;
+    case QG_RZ:
+        m[0][0] = std::polar(1.0, -0.5 * p[0]); m[0][1] = 0.0;
+        m[1][0] = 0.0; m[1][1] = std::polar(1.0, 0.5 * p[0]);
+        return;
+    case QG_U3:
+        m[0][0] = c;
+        m[0][1] = -std::polar(1.0, p[2]) * s;
+        m[1][0] = std::polar(1.0, p[1]) * s;
+        m[1][1] = std::polar(1.0, p[1] + p[2]) * c;
+        return;
+    }
+    m[0][0] = 1.0; m[0][1] = 0.0; m[1][0] = 0.0; m[1][1] = 1.0;
+}
+
+uint64_t required_qubits(const Gate &g) {
+    switch (g.op) {
+    case QG_H: case QG_X: case QG_RX: case QG_RY: case QG_U3: case QG_CX:
+        return 1ull << g.q1;
+    case QG_SWAP:
+        return (1ull << g.q0) | (1ull << g.q1);
+    }
+    return 0;
+}
+
+qg_status validate_circuit(const qg_circuit *c, int n_params, std::string *err) {
+    if (!c) { *err = "circuit is NULL"; return QG_EINVAL; }
+    const int n = c->n_qubits;
+    if (n < 1 || n > 34) { *err = "n_qubits must be in [1, 34], got " + std::to_string(n); return QG_EINVAL; }
+    if (c->n_gates < 0) { *err = "n_gates < 0"; return QG_EINVAL; }
+    if (c->n_gates > 0 && (!c->gate_type || !c->gate_param)) {
+        *err = "gate_type / gate_param is NULL";
+        return QG_EINVAL;
+    }
+    for (int g = 0; g < c->n_gates; ++g) {
+        const int op = c->gate_type[3 * g], q0 = c->gate_type[3 * g + 1], q1 = c->gate_type[3 * g + 2];
+        const double *p = c->gate_param + 3 * g;
+        const std::string at = " at gate " + std::to_string(g);
+        if (op < QG_H || op > QG_SWAP) { *err = "unknown gate code " + std::to_string(op) + at; return QG_EINVAL; }
+        if (q1 < 0 || q1 >= n) { *err = "qubit " + std::to_string(q1) + " out of range" + at; return QG_EINVAL; }
+        if (is_two_qubit(op)) {
+            if (q0 < 0 || q0 >= n) { *err = "qubit " + std::to_string(q0) + " out of range" + at; return QG_EINVAL; }
+            if (q0 == q1) { *err = "two-qubit gate with q0 == q1" + at; return QG_EINVAL; }
+        }
+        const int used = op == QG_U3 ? 3 : (op == QG_RX || op == QG_RY || op == QG_RZ || op == QG_CP) ? 1 : 0;
+        for (int k = 0; k < used; ++k)
+            if (!std::isfinite(p[k])) { *err = "non-finite parameter" + at; return QG_EINVAL; }
+        if (c->param_idx && c->param_idx[g] >= 0) {
+            if (!(op == QG_RX || op == QG_RY || op == QG_RZ || op == QG_CP)) {
+                *err = "trainable slot on a gate other than RX/RY/RZ/CP" + at;
+                return QG_EINVAL;
+            }
+            if (n_params >= 0 && c->param_idx[g] >= n_params) {
+                *err = "param_idx " + std::to_string(c->param_idx[g]) + " >= n_params" + at;
+                return QG_EINVAL;
+            }
+        }
+    }
+    return QG_OK;
+}
+
+std::vector<Gate> load_gates(const qg_circuit *c) {
+    std::vector<Gate> v(c->n_gates);
+    for (int g = 0; g < c->n_gates; ++g) {
+        Gate &x = v[g];
+        x.op = c->gate_type[3 * g];
+        x.q0 = c->gate_type[3 * g + 1];
+        x.q1 = c->gate_type[3 * g + 2];
+        for (int k = 0; k < 3; ++k) x.p[k] = c->gate_param[3 * g + k];
+        x.pidx = c->param_idx ? c->param_idx[g] : -1;
+    }
+    return v;
+}
+
+std::vector<Gate> execution_order(const std::vector<Gate> &g, bool reverse) {
+    std::vector<Gate> v(g);
+    if (reverse) std::reverse(v.begin(), v.end());
+    return v;
+}
+
+std::vector<PassRange> fuse(const std::vector<Gate> &g, const PlanConfig &cfg) {
+    std::vector<PassRange> out;
+    const int G = (int)g.size();
+    if (cfg.fusion == QG_FUSE_NONE) {
+        for (int i = 0; i < G; ++i) out.push_back({i, i + 1});
+        return out;
+    }
+    const int n = cfg.n;
+    const int b = std::min(n, cfg.tile_bits);
+    // Qubits below low_bits are always in a fused tile; when the whole state is one
+    // tile every qubit is.
+    const int low = n <= b ? n : std::min(cfg.low_bits, b);
+    const uint64_t low_mask = low >= 64 ? ~0ull : ((1ull << low) - 1);
+    const int max_high = n <= b ? 64 : std::min(cfg.max_high, b - low);
+    const int kMaxGatesPerPass = 4096;
+    const int kMaxGradPerPass = 64;  // bounds the adjoint partial-sum scratch
+    int begin = 0, grads = 0;
+    uint64_t high = 0;
+    for (int i = 0; i < G; ++i) {
+        const uint64_t req = required_qubits(g[i]) & ~low_mask;
+        const int gr = (cfg.reverse && g[i].pidx >= 0) ? 1 : 0;
+        if (i > begin && (popcount64(high | req) > max_high || i - begin >= kMaxGatesPerPass ||
+                          grads + gr > kMaxGradPerPass)) {
+            out.push_back({begin, i});
+            begin = i;
+            high = 0;
+            grads = 0;
+        }
+        high |= req;
+        grads += gr;
+    }
+    if (G > begin) out.push_back({begin, G});
+    return out;
+}
+
+Program build_program(const std::vector<Gate> &gates, const std::vector<PassRange> &ranges,
+                      const PlanConfig &cfg) {
+    Program prog;
+    const int n = cfg.n;
+    prog.pass_of_gate.assign(gates.size(), -1);
+    int grad_rows = 0;
+    for (size_t pi = 0; pi < ranges.size(); ++pi) {
+        const PassRange &r = ranges[pi];
+        std::vector<Item> items;
+        uint64_t req = 0;
+        const int grad_base = grad_rows;
+        for (int gi = r.g_begin; gi < r.g_end; ++gi) {
+            const Gate &g = gates[gi];
+            prog.pass_of_gate[gi] = (int)pi;
+            req |= required_qubits(g);
+            int row = -1;  // gradient row, local to the pass
+            if (cfg.reverse && g.pidx >= 0) {
+                row = grad_rows++ - grad_base;
+                prog.grad_row_slot.push_back(g.pidx);
+            }
+            gate_items(g, cfg.reverse, row, &items);
+        }
+        // ---- tile: required qubits, then the lowest remaining ones
+        const int b = std::min(n, cfg.tile_bits);
+        uint64_t tile = req;
+        for (int q = 0; q < n && popcount64(tile) < b; ++q) tile |= 1ull << q;
+        int tile_q[kMaxTileBits];
+        int pos_of[64];
+        for (int q = 0; q < 64; ++q) pos_of[q] = -1;
+        int nb = 0;
+        for (int q = 0; q < n; ++q)
+            if (tile >> q & 1) { pos_of[q] = nb; tile_q[nb++] = q; }
+        int rb = std::min(cfg.reg_bits, b);
+        if (b - rb > kMaxThreadBits) rb = b - kMaxThreadBits;
+        const int tb = b - rb;
+
+        // ---- fixed bits: tiles on which every op is the identity are skipped
+        uint64_t fixed = items.empty() ? 0 : ~0ull;
+        for (const Item &it : items) {
+            uint64_t cond = 0;
+            if (it.kind == OP_CMAT && pos_of[it.qc] < 0) cond = 1ull << it.qc;
+            if (it.kind == OP_DIAG2 || it.kind == OP_GRADP11) {
+                if (pos_of[it.qa] < 0) cond |= 1ull << it.qa;
+                if (pos_of[it.qc] < 0) cond |= 1ull << it.qc;
+            }
+            fixed &= cond;
+        }
+
+        PassDesc pd{};
+        pd.b = b;
+        pd.rb = rb;
+        pd.tb = tb;
+        pd.fixed_mask = fixed;
+        pd.fixed_val = fixed;
+        int free_bits = 0;
+        for (int q = 0; q < n; ++q) {
+            if ((tile >> q & 1) || (fixed >> q & 1)) continue;
+            if (pd.n_runs > 0 && pd.run_start[pd.n_runs - 1] + pd.run_len[pd.n_runs - 1] == q) {
+                pd.run_len[pd.n_runs - 1]++;
+            } else {
+                pd.run_start[pd.n_runs] = q;
+                pd.run_len[pd.n_runs] = 1;
+                pd.n_runs++;
+            }
+            free_bits++;
+        }
+        pd.n_tiles = 1ull << free_bits;
+        pd.phase_begin = (int)prog.phases.size();
+
+        // ---- phases: register positions must hold every mixing op's target
+        auto ref = [&](int q) { return pos_of[q] >= 0 ? pos_of[q] : qref_global(q); };
+        size_t i = 0;
+        bool first = true;
+        while (i < items.size() || first) {
+            std::vector<int> S;
+            for (size_t j = i; j < items.size() && (int)S.size() < rb; ++j) {
+                int q = needs_register(items[j]);
+                if (q < 0) continue;
+                int p = pos_of[q];
+                if (std::find(S.begin(), S.end(), p) == S.end()) S.push_back(p);
+            }
+            for (int p = b - 1; p >= 0 && (int)S.size() < rb; --p)
+                if (std::find(S.begin(), S.end(), p) == S.end()) S.push_back(p);
+            PhaseDesc ph{};
+            std::vector<int> thr;
+            for (int p = 0; p < b; ++p)
+                if (std::find(S.begin(), S.end(), p) == S.end()) thr.push_back(p);
+            for (int k = 0; k < tb; ++k) {
+                ph.thr_goff[k] = 1ull << tile_q[thr[k]];
+                ph.thr_poff[k] = 1u << thr[k];
+            }
+            for (int j = 0; j < rb; ++j) {
+                ph.reg_goff[j] = 1ull << tile_q[S[j]];
+                ph.reg_poff[j] = 1u << S[j];
+            }
+            ph.op_begin = (int)prog.ops.size();
+            for (; i < items.size(); ++i) {
+                const Item &it = items[i];
+                const int q = needs_register(it);
+                int slot = -1;
+                if (q >= 0) {
+                    auto f = std::find(S.begin(), S.end(), pos_of[q]);
+                    if (f == S.end()) break;  // next phase
+                    slot = (int)(f - S.begin());
+                }
+                DevOp op{};
+                op.kind = it.kind;
+                op.g = it.g;
+                std::memcpy(op.m, it.m, sizeof op.m);
+                switch (it.kind) {
+                case OP_MAT: case OP_GRADX: case OP_GRADY:
+                    op.a = slot;
+                    break;
+                case OP_CMAT:
+                    op.a = slot;
+                    op.c = ref(it.qc);
+                    break;
+                case OP_DIAG1: case OP_GRADZ:
+                    op.a = ref(it.qa);
+                    break;
+                case OP_DIAG2: case OP_GRADP11:
+                    op.a = ref(it.qa);
+                    op.c = ref(it.qc);
+                    break;
+                }
+                prog.ops.push_back(op);
+            }
+            ph.op_end = (int)prog.ops.size();
+            prog.phases.push_back(ph);
+            first = false;
+        }
+        pd.n_phase = (int)prog.phases.size() - pd.phase_begin;
+        pd.grad_base = grad_base;
+        pd.n_grad = grad_rows - grad_base;
+        const int64_t waves = std::max(1, (1 << tb) / 64);
+        prog.max_grad_part = std::max<int64_t>(prog.max_grad_part, (int64_t)pd.n_tiles * waves * pd.n_grad);
+        prog.passes.push_back(pd);
+    }
+    return prog;
+}
+
+}  // namespace qg

@@ -1,0 +1,71 @@
+// qg_plan.h -- host-side circuit validation, fusion planning and device-program building.
+#pragma once
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "../../include/qg.h"
+#include "qg_internal.h"
+
+namespace qg {
+
+using cd = std::complex<double>;
+
+struct Gate {
+    int op, q0, q1;
+    double p[3];
+    int pidx;
+};
+
+// Tiling and fusion knobs of one plan.
+struct PlanConfig {
+    int n = 0;
+    bool c64 = false;
+    int tile_bits = 12;   // qubits per tile (capped at n)
+    int reg_bits = 4;     // tile positions held in registers (amplitudes per thread = 2^reg_bits)
+    int low_bits = 7;     // lowest qubits always in a fused tile (coalesced runs)
+    int max_high = 5;     // fused pass: distinct required qubits >= low_bits
+    int fusion = QG_FUSE_GREEDY;
+    bool reverse = false; // adjoint sweep: reversed gates, daggered, with gradient ops
+};
+
+PlanConfig default_config(int n, bool c64, int fusion);
+
+// One fused pass as a gate range [g_begin, g_end) in execution order.
+struct PassRange {
+    int g_begin, g_end;
+};
+
+struct Program {
+    std::vector<PassDesc> passes;
+    std::vector<PhaseDesc> phases;
+    std::vector<DevOp> ops;
+    std::vector<int> pass_of_gate;   // index into execution order
+    std::vector<int> grad_row_slot;  // adjoint: parameter slot of each gradient row
+    int64_t max_grad_part = 0;       // adjoint: largest per-pass partial-sum block (doubles)
+};
+
+// Validates a circuit (qubits in range, q0 != q1, known code, finite params,
+// trainable slots only on RX/RY/RZ/CP and below n_params when n_params >= 0).
+// Returns QG_OK or QG_EINVAL with *err set.
+qg_status validate_circuit(const qg_circuit *c, int n_params, std::string *err);
+
+std::vector<Gate> load_gates(const qg_circuit *c);
+
+// Execution-order gate list (reversed for adjoint sweeps).
+std::vector<Gate> execution_order(const std::vector<Gate> &g, bool reverse);
+
+// Fusion: partition execution-order gates into passes.
+std::vector<PassRange> fuse(const std::vector<Gate> &g, const PlanConfig &cfg);
+
+// Device program for the given pass partition.
+Program build_program(const std::vector<Gate> &g, const std::vector<PassRange> &passes,
+                      const PlanConfig &cfg);
+
+// 2x2 matrix of a single-qubit gate (textbook forms, header of qg.h).
+void gate_matrix(int op, const double *p, cd m[2][2]);
+
+// Required tile qubits of a gate (targets of non-diagonal ops) as a bit mask.
+uint64_t required_qubits(const Gate &g);
+
+}  // namespace qg

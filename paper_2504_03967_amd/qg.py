@@ -1,0 +1,200 @@
+"""ctypes binding of libqg.so (the C ABI declared in include/qg.h).
+
+Argument marshalling only: every step of the simulation runs in the library's
+HIP kernels.  PyTorch supplies device memory and the stream.  The module fails
+loudly when the built library is missing; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqg.so")
+
+QG_OK, QG_EINVAL, QG_ENOMEM, QG_EDEVICE, QG_EUNSUPPORTED, QG_EINTERNAL = 0, -1, -2, -3, -4, -5
+C64, C128 = 0, 1
+FUSE_NONE, FUSE_GREEDY, FUSE_LEARNED = 0, 1, 2
+OBS_ZZ_CHAIN, OBS_CSR = 0, 1
+
+EXPORTS = (
+    "qg_state_alloc", "qg_state_free", "qg_state_reset", "qg_state_set_stream", "qg_state_info",
+    "qg_apply_circuit", "qg_probs", "qg_sample", "qg_expval", "qg_adjoint_grad", "qg_batch_expval",
+    "qg_plan_passes", "qg_last_error", "qg_version",
+)
+
+
+class QGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"qg status {status}: {msg}")
+        self.status = status
+
+
+class _Circuit(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32),
+                ("gate_type", ctypes.c_void_p), ("gate_param", ctypes.c_void_p),
+                ("param_idx", ctypes.c_void_p)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(python -m paper_2504_03967_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    sig = {
+        "qg_state_alloc": [ctypes.c_int, ctypes.c_int, P, ctypes.c_size_t, P, P],
+        "qg_state_free": [P],
+        "qg_state_reset": [P],
+        "qg_state_set_stream": [P, P],
+        "qg_state_info": [P, P, P, P],
+        "qg_apply_circuit": [P, P, ctypes.c_int],
+        "qg_probs": [P, P, I64, P],
+        "qg_sample": [P, I64, U64, P],
+        "qg_expval": [P, P, P, ctypes.c_int, P, P],
+        "qg_adjoint_grad": [P, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, P, P, P],
+        "qg_batch_expval": [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P],
+        "qg_plan_passes": [P, ctypes.c_int, ctypes.c_int, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.qg_last_error.restype = ctypes.c_char_p
+    lib.qg_last_error.argtypes = []
+    lib.qg_version.restype = ctypes.c_char_p
+    lib.qg_version.argtypes = []
+    return lib
+
+
+lib = _load()
+
+
+def _check(st: int) -> None:
+    if st != QG_OK:
+        raise QGError(st, lib.qg_last_error().decode())
+
+
+def version() -> str:
+    return lib.qg_version().decode()
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class CircuitArgs:
+    """Keeps the numpy arrays of one circuit alive while the C struct points at them."""
+
+    def __init__(self, circ):
+        self.gt = np.ascontiguousarray(circ.gate_type, dtype=np.int32).reshape(-1, 3)
+        self.gp = np.ascontiguousarray(circ.gate_param, dtype=np.float64).reshape(-1, 3)
+        pidx = getattr(circ, "param_idx", None)
+        self.pi = None if pidx is None else np.ascontiguousarray(pidx, dtype=np.int32)
+        self.c = _Circuit(int(circ.n_qubits), int(self.gt.shape[0]), self.gt.ctypes.data, self.gp.ctypes.data,
+                          None if self.pi is None else self.pi.ctypes.data)
+
+    @property
+    def ptr(self):
+        return ctypes.byref(self.c)
+
+
+def _dtype_code(dtype) -> int:
+    if dtype in (C64, "c64", torch.complex64):
+        return C64
+    if dtype in (C128, "c128", torch.complex128):
+        return C128
+    raise ValueError(f"unknown dtype {dtype!r}")
+
+
+class State:
+    """A 2^n-amplitude state in a torch-owned device buffer (borrowed by the library)."""
+
+    def __init__(self, n: int, dtype="c128", device: str = "cuda", stream: Optional[torch.cuda.Stream] = None):
+        self.n = int(n)
+        self.code = _dtype_code(dtype)
+        tdt = torch.complex64 if self.code == C64 else torch.complex128
+        self.tensor = torch.empty(1 << self.n, dtype=tdt, device=device)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(lib.qg_state_alloc(self.n, self.code, ctypes.c_void_p(self.tensor.data_ptr()),
+                                  self.tensor.numel() * self.tensor.element_size(), _stream_handle(stream),
+                                  ctypes.byref(h)))
+        self.handle = h
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib.qg_state_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream: Optional[torch.cuda.Stream]) -> None:
+        self._stream = stream
+        _check(lib.qg_state_set_stream(self.handle, _stream_handle(stream)))
+
+    def reset(self) -> "State":
+        _check(lib.qg_state_reset(self.handle))
+        return self
+
+    def apply(self, circ, fusion: int = FUSE_GREEDY) -> "State":
+        ca = CircuitArgs(circ)
+        _check(lib.qg_apply_circuit(self.handle, ca.ptr, int(fusion)))
+        return self
+
+    def probs(self, idx: Optional[Sequence[int]] = None) -> torch.Tensor:
+        if idx is None:
+            out = torch.empty(1 << self.n, dtype=torch.float64, device=self.tensor.device)
+            _check(lib.qg_probs(self.handle, None, 0, ctypes.c_void_p(out.data_ptr())))
+            return out
+        ix = np.ascontiguousarray(idx, dtype=np.uint64)
+        out = torch.empty(ix.size, dtype=torch.float64, device=self.tensor.device)
+        _check(lib.qg_probs(self.handle, ix.ctypes.data, ix.size, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def sample(self, shots: int, seed: int) -> torch.Tensor:
+        """Shot indices (int64 tensor holding the uint64 values)."""
+        out = torch.empty(max(int(shots), 0), dtype=torch.int64, device=self.tensor.device)
+        _check(lib.qg_sample(self.handle, int(shots), int(seed) & ((1 << 64) - 1), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def expval(self, masks: Sequence[int], coeffs: Optional[Sequence[float]] = None):
+        m = np.ascontiguousarray(masks, dtype=np.uint64)
+        terms = torch.empty(m.size, dtype=torch.float64, device=self.tensor.device)
+        total = torch.empty(1, dtype=torch.float64, device=self.tensor.device)
+        c = None if coeffs is None else np.ascontiguousarray(coeffs, dtype=np.float64)
+        _check(lib.qg_expval(self.handle, m.ctypes.data, None if c is None else c.ctypes.data, m.size,
+                             ctypes.c_void_p(terms.data_ptr()),
+                             None if c is None else ctypes.c_void_p(total.data_ptr())))
+        return terms, (None if c is None else total[0])
+
+
+def adjoint_grad(circ, masks, coeffs, n_params: int, dtype="c128", stream=None):
+    """(value, grad) tensors of f = sum_m coeff_m <Z_m> by the library's adjoint sweep."""
+    ca = CircuitArgs(circ)
+    m = np.ascontiguousarray(masks, dtype=np.uint64)
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    val = torch.empty(1, dtype=torch.float64, device="cuda")
+    grad = torch.empty(max(n_params, 1), dtype=torch.float64, device="cuda")
+    _check(lib.qg_adjoint_grad(ca.ptr, _dtype_code(dtype), m.ctypes.data, c.ctypes.data, m.size, int(n_params),
+                               _stream_handle(stream), ctypes.c_void_p(val.data_ptr()),
+                               ctypes.c_void_p(grad.data_ptr())))
+    return val[0], grad[:n_params]
+
+
+def plan_passes(circ, dtype="c128", fusion: int = FUSE_GREEDY):
+    """(pass index of each gate, number of passes) of the library's plan (host only)."""
+    ca = CircuitArgs(circ)
+    pog = np.zeros(max(ca.gt.shape[0], 1), dtype=np.int32)
+    npass = ctypes.c_int32()
+    _check(lib.qg_plan_passes(ca.ptr, _dtype_code(dtype), int(fusion), pog.ctypes.data, ctypes.byref(npass)))
+    return pog[:ca.gt.shape[0]], int(npass.value)

@@ -1,0 +1,231 @@
+"""GPU path (libqg.so through its C ABI) against the FP64 oracle, element by element.
+
+Tolerances: max amplitude error 1e-12 (complex128) / 1e-5 (complex64);
+expectations per Z-string term to the same; shots by chi-square p > 0.01 and,
+with the shared Philox stream, >= 99.9 % of shots identical to the oracle's.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.stats import chi2
+
+import oracle
+from paper_2504_03967_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def qg():
+    from paper_2504_03967_amd import qg as lib
+    assert torch.cuda.is_available()
+    return lib
+
+
+def run(qg, circ, dtype="c128", fusion=1):
+    st = qg.State(circ.n_qubits, dtype)
+    st.apply(circ, fusion)
+    return st
+
+
+def host(st):
+    torch.cuda.synchronize()
+    return st.tensor.cpu().numpy().astype(np.complex128)
+
+
+def prep_layer(n, seed):
+    rng = W.SplitMix64(seed)
+    b = W.CircuitBuilder(n)
+    for q in range(n):
+        b.g1(W.U3, q, *(2 * math.pi * rng.uniform(3)))
+    return b.build()
+
+
+def chi_square_p(counts, p, shots):
+    obs, exp_ = [], []
+    o = e = 0.0
+    for c, pi in zip(counts, p):
+        o += c
+        e += pi * shots
+        if e >= 5:
+            obs.append(o); exp_.append(e); o = e = 0.0
+    if e > 0 and obs:
+        obs[-1] += o; exp_[-1] += e
+    obs, exp_ = np.array(obs), np.array(exp_)
+    return chi2.sf(np.sum((obs - exp_) ** 2 / exp_), len(obs) - 1)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7, 9, 13, 15])
+def test_every_op_at_every_position(qg, n, dtype):
+    rng = np.random.default_rng(n)
+    for op in range(10):
+        if op in W.TWO_QUBIT and n < 2:
+            continue
+        b = W.CircuitBuilder(n)
+        prep = prep_layer(n, 17 * n + op)
+        for (o, q0, q1), p in zip(prep.gate_type, prep.gate_param):
+            b.add(o, q0, q1, p)
+        for t in range(n):
+            for c in (range(n) if op in W.TWO_QUBIT else [-1]):
+                if c == t:
+                    continue
+                b.add(op, c, t, rng.uniform(0, 2 * math.pi, 3))
+        circ = b.build()
+        ref = oracle.simulate(circ)
+        for fusion in (0, 1):
+            got = host(run(qg, circ, dtype, fusion))
+            err = np.max(np.abs(got - ref))
+            assert err < TOL[dtype] * max(1, circ.n_gates / 200), (op, fusion, err)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 7, 12, 16, 20])
+def test_random_circuits(qg, n, dtype):
+    circ = W.random_circuit(n, 300, seed=500 + n)
+    ref = oracle.simulate(circ)
+    for fusion in (0, 1):
+        got = host(run(qg, circ, dtype, fusion))
+        assert np.max(np.abs(got - ref)) < TOL[dtype], fusion
+
+
+def test_config1_outputs(qg):
+    circ = W.config1()
+    st = run(qg, circ, "c128", 1)
+    psi = oracle.simulate(circ)
+    assert np.max(np.abs(host(st) - psi)) < 1e-12
+    p_ref = oracle.probs(psi)
+    assert np.max(np.abs(st.probs().cpu().numpy() - p_ref)) < 1e-12
+    masks = W.zz_chain_masks(12)
+    terms, total = st.expval(masks, np.ones(11))
+    ev = oracle.expval(psi, masks)
+    assert np.max(np.abs(terms.cpu().numpy() - ev)) < 1e-12
+    assert abs(float(total) - ev.sum()) < 11e-12
+    seed = W.SEED_BASE
+    shots = st.sample(10000, seed).cpu().numpy().astype(np.uint64)
+    ref_shots = oracle.sample(psi, 10000, seed)
+    assert np.mean(shots == ref_shots) >= 0.999
+    counts = np.bincount(shots.astype(np.int64), minlength=4096)
+    assert chi_square_p(counts, p_ref, 10000) > 0.01
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_config2_qcrank_closed_form_and_shots(qg, dtype):
+    circ, p = W.config2()
+    st = run(qg, circ, dtype, 1)
+    got = host(st)
+    a = np.arange(1 << 16) & 0xFF
+    amp = np.full(1 << 16, 2 ** -4.0)
+    for d in range(8):
+        bit = (np.arange(1 << 16) >> (8 + d)) & 1
+        amp *= np.where(bit == 0, np.sqrt(p[d, a]), np.sqrt(1 - p[d, a]))
+    assert np.max(np.abs(got - amp)) < TOL[dtype]
+    psi = oracle.simulate(circ)
+    assert np.max(np.abs(got - psi)) < TOL[dtype]
+    shots = st.sample(1_000_000, W.SEED_BASE + 1).cpu().numpy().astype(np.int64)
+    counts = np.bincount(shots, minlength=1 << 16)
+    assert chi_square_p(counts, np.abs(psi) ** 2, 1_000_000) > 0.01
+    if dtype == "c128":
+        ref = oracle.sample(psi, 1_000_000, W.SEED_BASE + 1).astype(np.int64)
+        assert np.mean(shots == ref) >= 0.999
+    # reconstruction of the synthetic pixels: p_hat(d, a) = counts(a, d = 0) / counts(a)
+    addr = shots & 0xFF
+    n_a = np.bincount(addr, minlength=256)
+    for d in range(8):
+        zero = ((shots >> (8 + d)) & 1) == 0
+        n0 = np.bincount(addr[zero], minlength=256)
+        phat = n0 / n_a
+        z = (phat - p[d]) / np.sqrt(np.maximum(p[d] * (1 - p[d]), 1e-12) / n_a)
+        assert np.all(np.abs(z) < 5.5)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_config3_shape_reduced(qg, dtype):
+    n = 20
+    circ = W.config3(n, layers=20)
+    st = run(qg, circ, dtype, 1)
+    psi = oracle.simulate(circ)
+    idx = W.config3_indices(n)
+    p = st.probs(idx).cpu().numpy()
+    assert np.max(np.abs(p - np.abs(psi[idx.astype(np.int64)]) ** 2)) < TOL[dtype]
+    masks = np.array([0, (1 << 0) | (1 << (n - 1))], dtype=np.uint64)
+    terms, _ = st.expval(masks)
+    ref = oracle.expval(psi, masks)
+    assert np.max(np.abs(terms.cpu().numpy() - ref)) < TOL[dtype]
+    assert abs(terms[0].item() - 1) < (1e-13 if dtype == "c128" else 1e-5)
+
+
+def test_expval_many_terms_and_weights(qg):
+    n = 14
+    circ = W.random_circuit(n, 200, seed=3)
+    st = run(qg, circ)
+    psi = oracle.simulate(circ)
+    rng = np.random.default_rng(0)
+    masks = rng.integers(0, 1 << n, 41).astype(np.uint64)
+    coeffs = rng.normal(size=41)
+    terms, total = st.expval(masks, coeffs)
+    ref = oracle.expval(psi, masks)
+    assert np.max(np.abs(terms.cpu().numpy() - ref)) < 1e-12
+    assert abs(float(total) - np.dot(coeffs, ref)) < 1e-11
+
+
+def test_probs_index_list_ragged(qg):
+    n = 18
+    circ = W.random_circuit(n, 100, seed=4)
+    st = run(qg, circ)
+    psi = oracle.simulate(circ)
+    idx = np.random.default_rng(1).integers(0, 1 << n, 1003).astype(np.uint64)
+    p = st.probs(idx).cpu().numpy()
+    assert np.max(np.abs(p - np.abs(psi[idx.astype(np.int64)]) ** 2)) < 1e-12
+    full = st.probs().cpu().numpy()
+    assert np.max(np.abs(full - np.abs(psi) ** 2)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 6, 7, 13])
+def test_sampling_small_and_degenerate(qg, n):
+    b = W.CircuitBuilder(n).g1(W.X, n - 1)
+    st = run(qg, b.build())
+    s = st.sample(777, 5).cpu().numpy()
+    assert np.all(s == (1 << (n - 1)))
+    assert st.sample(0, 5).numel() == 0
+    circ = W.random_circuit(n, 50, seed=n)
+    st = run(qg, circ)
+    psi = oracle.simulate(circ)
+    got = st.sample(5000, 99).cpu().numpy().astype(np.uint64)
+    assert np.mean(got == oracle.sample(psi, 5000, 99)) >= 0.999
+
+
+def test_reset_and_repeat_are_bitwise_deterministic(qg):
+    circ = W.config3(16, layers=10)
+    st = run(qg, circ)
+    a = host(st)
+    t1, _ = st.expval(W.zz_chain_masks(16))
+    st.reset()
+    st.apply(circ, 1)
+    b = host(st)
+    t2, _ = st.expval(W.zz_chain_masks(16))
+    assert np.array_equal(a, b)
+    assert torch.equal(t1, t2)
+
+
+def test_validation_errors_leave_state_untouched(qg):
+    st = run(qg, W.config1())
+    before = host(st)
+    bad = W.CircuitBuilder(12).g2(W.CX, 3, 3).build()
+    with pytest.raises(qg.QGError) as e:
+        st.apply(bad)
+    assert e.value.status == qg.QG_EINVAL and "q0 == q1" in str(e.value)
+    with pytest.raises(qg.QGError):
+        st.apply(W.CircuitBuilder(11).g1(W.H, 0).build())
+    with pytest.raises(qg.QGError):
+        st.expval([1 << 12])
+    with pytest.raises(qg.QGError):
+        st.probs([1 << 12])
+    nan = W.CircuitBuilder(12).g1(W.RX, 0, float("nan")).build()
+    with pytest.raises(qg.QGError):
+        st.apply(nan)
+    assert np.array_equal(host(st), before)
