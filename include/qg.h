@@ -154,15 +154,34 @@ qg_status qg_adjoint_grad(const qg_circuit *c, qg_dtype dtype, const uint64_t *z
                           double *out_value, double *out_grad);
 
 /* Batched form (the paper's parallel / multi-circuit mode, Sec. 2.4): n_circ
- * independent circuits of possibly different qubit counts, all from |0...0>,
- * run by one persistent launch; out[c] = sum_{i<n_c-1} <Z_i Z_{i+1}> of
+ * independent circuits of possibly different qubit counts (1..22), each from
+ * |0...0>, run by one persistent launch; out[c] = sum_{i<n_c-1} <Z_i Z_{i+1}> of
  * circuit c (obs_kind QG_OBS_ZZ_CHAIN), or sum over its CSR terms
- * obs_off[c]..obs_off[c+1] of coeff * <Z_zmask> (QG_OBS_CSR).
- * out: device [n_circ].  Circuits of up to 20 qubits. */
+ * k in [obs_off[c], obs_off[c+1]) of coeff[k] <Z_{zmask[k]}> (QG_OBS_CSR; host
+ * arrays, obs_off has n_circ + 1 entries starting at 0).  Circuits whose state
+ * fits one tile (2^12 amplitudes in complex128, 2^13 in complex64) never
+ * touch HBM; larger ones use a per-workgroup scratch state.  out: device
+ * [n_circ] (written when the launch runs). */
 typedef enum { QG_OBS_ZZ_CHAIN = 0, QG_OBS_CSR = 1 } qg_obs_kind;
+
+/* One-shot: plan, upload, launch, release (the release waits for the stream). */
 qg_status qg_batch_expval(const qg_circuit *circs, int n_circ, qg_dtype dtype, int obs_kind,
                           const int64_t *obs_off, const uint64_t *zmask, const double *coeff,
                           void *hip_stream, double *out);
+
+/* Reusable batch: qg_batch_create plans and uploads every circuit, allocates the
+ * scratch states and, when hip_stream is not the NULL stream, captures the
+ * launch into a HIP graph; qg_batch_launch replays it (or launches directly) on
+ * that stream.  qg_batch_set_params uploads new angles for circuits with the
+ * same gate structure (codes and qubits; QG_EINVAL otherwise), enqueued on the
+ * stream before the next launch.  qg_batch_free waits for the stream. */
+typedef struct qg_batch qg_batch;
+qg_status qg_batch_create(const qg_circuit *circs, int n_circ, qg_dtype dtype, int obs_kind,
+                          const int64_t *obs_off, const uint64_t *zmask, const double *coeff,
+                          void *hip_stream, double *out, qg_batch **handle);
+qg_status qg_batch_set_params(qg_batch *b, const qg_circuit *circs);
+qg_status qg_batch_launch(qg_batch *b);
+qg_status qg_batch_free(qg_batch *b);
 
 /* Plan inspection (host only, no device needed): the pass each gate of the
  * circuit is executed in under fusion_mode, written to pass_of_gate[n_gates]
@@ -170,6 +189,19 @@ qg_status qg_batch_expval(const qg_circuit *circs, int n_circ, qg_dtype dtype, i
  * increasing order and cover every gate exactly once, in order. */
 qg_status qg_plan_passes(const qg_circuit *c, qg_dtype dtype, int fusion_mode,
                          int32_t *pass_of_gate, int32_t *n_passes);
+
+/* Process-wide planner tuning (not part of the paper's method; performance only,
+ * results are identical up to rounding for every setting).  Keys:
+ *   tile_bits_c128 / tile_bits_c64   qubits per tile (amplitudes streamed per workgroup)
+ *   reg_bits_c128 / reg_bits_c64     amplitudes per thread = 2^reg_bits
+ *   low_bits_c128 / low_bits_c64     lowest qubits kept in every fused tile
+ *   max_high_c128 / max_high_c64     fusion width: targets >= low_bits per pass
+ *   nt                               1 = non-temporal state loads/stores
+ *   swz_bits                         tile-order swizzle of the launch
+ * Errors: QG_EINVAL for an unknown key or a value out of range.  Not
+ * thread-safe against concurrent planning. */
+qg_status qg_set_tuning(const char *key, int64_t value);
+qg_status qg_get_tuning(const char *key, int64_t *value);
 
 /* Message describing the calling thread's last failed call ("" if none). */
 const char *qg_last_error(void);

@@ -122,33 +122,44 @@ struct Pack {
     size_t add(const std::vector<T> &v) { return add(v.data(), v.size() * sizeof(T)); }
 };
 
+// Upload ring: kRing (pinned host, device) buffer pairs used in turn, so the
+// host only waits for the copy issued kRing uploads ago.  A device slot is
+// rewritten by a copy that the stream orders after every kernel already
+// enqueued, so kernels reading an older upload are never overtaken.
+constexpr int kRing = 4;
+
 struct Ctx {
     hipStream_t stream = nullptr;
-    Staging stage;
-    DevBuf upload;   // uploaded program / index / mask tables
+    Staging stage[kRing];
+    DevBuf upload[kRing];
+    int slot = 0;
     DevBuf work;     // partial sums, sampling tree
     DevBuf work2;    // gradient rows
     ~Ctx() {
-        stage.release();
-        upload.release();
+        for (int k = 0; k < kRing; ++k) {
+            stage[k].release();
+            upload[k].release();
+        }
         work.release();
         work2.release();
     }
-    // Copies the pack to `upload` on the stream; returns the device base pointer.
+    // Copies the pack to a device upload slot on the stream; returns its device address.
     hipError_t push(const Pack &pk, unsigned char **dev) {
         const size_t n = pk.bytes.size();
-        hipError_t e = upload.ensure(n ? n : 1, stream);
+        const int k = slot;
+        slot = (slot + 1) % kRing;
+        hipError_t e = upload[k].ensure(n ? n : 1, stream);
         if (e != hipSuccess) return e;
-        *dev = static_cast<unsigned char *>(upload.p);
+        *dev = static_cast<unsigned char *>(upload[k].p);
         if (!n) return hipSuccess;
-        e = stage.ready(n);
+        e = stage[k].ready(n);
         if (e != hipSuccess) return e;
-        std::memcpy(stage.h, pk.bytes.data(), n);
-        e = hipMemcpyAsync(upload.p, stage.h, n, hipMemcpyHostToDevice, stream);
+        std::memcpy(stage[k].h, pk.bytes.data(), n);
+        e = hipMemcpyAsync(upload[k].p, stage[k].h, n, hipMemcpyHostToDevice, stream);
         if (e != hipSuccess) return e;
-        e = hipEventRecord(stage.ev, stream);
+        e = hipEventRecord(stage[k].ev, stream);
         if (e != hipSuccess) return e;
-        stage.pending = true;
+        stage[k].pending = true;
         return hipSuccess;
     }
 };
@@ -156,28 +167,57 @@ struct Ctx {
 size_t amp_bytes(qg_dtype dt) { return dt == QG_C64 ? 8 : 16; }
 int max_qubits(qg_dtype dt) { return dt == QG_C64 ? 34 : 33; }
 
-// Runs a program's passes on psi (and lam when ns == 2) with the uploaded copy at dev.
+bool fits_inline(const Program &prog, const PassDesc &pd) {
+    if (pd.n_phase > kInlinePhases) return false;
+    const PhaseDesc &first = prog.phases[pd.phase_begin];
+    const PhaseDesc &last = prog.phases[pd.phase_begin + pd.n_phase - 1];
+    return last.op_end - first.op_begin <= kInlineOps;
+}
+
+void make_inline(const Program &prog, const PassDesc &pd, InlineProg *out) {
+    std::memset(out, 0, sizeof *out);
+    out->pass = pd;
+    out->pass.phase_begin = 0;
+    const int op0 = prog.phases[pd.phase_begin].op_begin;
+    for (int k = 0; k < pd.n_phase; ++k) {
+        out->phases[k] = prog.phases[pd.phase_begin + k];
+        out->phases[k].op_begin -= op0;
+        out->phases[k].op_end -= op0;
+    }
+    const int n_ops = prog.phases[pd.phase_begin + pd.n_phase - 1].op_end - op0;
+    for (int i = 0; i < n_ops; ++i) out->ops[i] = prog.ops[op0 + i];
+}
+
+// Runs a program's passes on psi (and lam when ns == 2, writing gradient rows).
+// Small passes travel as kernel arguments; the rest read one uploaded copy.
 qg_status run_program(Ctx &cx, bool c64, const Program &prog, void *psi, void *lam, double *rows_out) {
     if (prog.passes.empty()) return QG_OK;
-    Pack pk;
-    const size_t pass_off = pk.add(prog.passes);
-    const size_t phase_off = pk.add(prog.phases);
-    const size_t op_off = pk.add(prog.ops);
+    bool need_upload = false;
+    for (const PassDesc &pd : prog.passes) need_upload |= !fits_inline(prog, pd);
+    size_t pass_off = 0, phase_off = 0, op_off = 0;
     unsigned char *dev = nullptr;
-    HIP_TRY(cx.push(pk, &dev), "upload program");
+    if (need_upload) {
+        Pack pk;
+        pass_off = pk.add(prog.passes);
+        phase_off = pk.add(prog.phases);
+        op_off = pk.add(prog.ops);
+        HIP_TRY(cx.push(pk, &dev), "upload program");
+    }
     const int ns = lam ? 2 : 1;
     double *gpart = nullptr;
-    int64_t gstride = 0;
     if (ns == 2 && prog.max_grad_part > 0) {
         HIP_TRY(cx.work.ensure(prog.max_grad_part * sizeof(double), cx.stream), "allocate gradient partials");
         gpart = static_cast<double *>(cx.work.p);
     }
+    InlineProg inl;
     for (size_t p = 0; p < prog.passes.size(); ++p) {
         const PassDesc &pd = prog.passes[p];
         const int64_t waves = pd.tb >= 6 ? (int64_t(1) << pd.tb) / 64 : 1;
-        gstride = (int64_t)pd.n_tiles * waves;
-        HIP_TRY(launch_tile(c64, pd, dev, pass_off, phase_off, op_off, (int)p, ns, psi, lam, gpart, gstride,
-                            cx.stream),
+        const int64_t gstride = (int64_t)pd.n_tiles * waves;
+        const bool small = fits_inline(prog, pd);
+        if (small) make_inline(prog, pd, &inl);
+        HIP_TRY(launch_tile(c64, pd, small ? &inl : nullptr, dev, pass_off, phase_off, op_off, (int)p, ns, psi, lam,
+                            gpart, gstride, cx.stream),
                 "tile kernel launch");
         if (ns == 2 && pd.n_grad > 0) {
             HIP_TRY(launch_grad_rows(gpart, gstride, gstride, pd.n_grad, rows_out + pd.grad_base, cx.stream),
@@ -212,11 +252,210 @@ struct qg_state {
     bool c64() const { return dt == QG_C64; }
 };
 
+namespace {
+
+constexpr int kBatchMaxQubits = 22;
+
+PlanConfig batch_config(int n, bool c64) {
+    PlanConfig cfg = default_config(n, c64, QG_FUSE_GREEDY);
+    cfg.tile_bits = c64 ? 13 : 12;
+    cfg.reg_bits = c64 ? 5 : 4;
+    cfg.low_bits = c64 ? 8 : 7;
+    cfg.max_high = 5;
+    cfg.flags = 0;       // states are re-read by the same workgroup: keep them cacheable
+    cfg.swz_bits = 0;
+    cfg.max_gates_per_pass = n <= cfg.tile_bits ? (1 << 30) : 4096;
+    clamp_config(&cfg);
+    return cfg;
+}
+
+// Plans one circuit of a batch.  Circuits narrower than the kernel's register
+// bits are planned on max(n, reg_bits) qubits; the extra qubits stay |0>.
+Program plan_batch_circuit(const qg_circuit &q, bool c64) {
+    qg_circuit w = q;
+    const int rb = c64 ? 5 : 4;
+    w.n_qubits = std::max(q.n_qubits, rb);
+    PlanConfig cfg = batch_config(w.n_qubits, c64);
+    std::vector<Gate> gl = load_gates(&w);
+    std::vector<PassRange> ranges = fuse(gl, cfg);
+    if (ranges.empty()) ranges.push_back({0, 0});  // identity pass keeps control flow uniform
+    return build_program(gl, ranges, cfg);
+}
+
+struct BatchDev {
+    DevBuf buf;
+    size_t off_ops = 0;
+    void *p_ops() { return static_cast<unsigned char *>(buf.p) + off_ops; }
+};
+
+struct CircShape {
+    int n, g;
+    size_t row0;
+};
+
+}  // namespace
+
+struct qg_batch {
+    bool c64 = false;
+    int n_circ = 0;
+    int obs_kind = 0;
+    int rb = 4;
+    double *out = nullptr;
+    Ctx cx;
+    BatchDev dev;
+    DevBuf scratch;
+    Staging ops_stage;
+    BatchLaunch L{};
+    std::vector<DevOp> host_ops;
+    std::vector<CircShape> shape;
+    std::vector<int32_t> gate_rows;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~qg_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        ops_stage.release();
+        dev.buf.release();
+        scratch.release();
+    }
+};
+
+namespace {
+
+qg_status batch_build(qg_batch *b, const qg_circuit *circs, const int64_t *obs_off, const uint64_t *zmask,
+                      const double *coeff, int *n_big_out) {
+    const int nc = b->n_circ;
+    std::vector<BatchCirc> bc(nc);
+    std::vector<PassDesc> passes;
+    std::vector<PhaseDesc> phases;
+    std::vector<DevOp> ops;
+    std::vector<double> cost(nc);
+    int n_big = 0, n_big_count = 0;
+    const int tile_bits = b->c64 ? 13 : 12;
+    b->rb = b->c64 ? 5 : 4;
+    for (int c = 0; c < nc; ++c) {
+        const qg_circuit &q = circs[c];
+        Program prog = plan_batch_circuit(q, b->c64);
+        for (PassDesc &pd : prog.passes) {
+            if (pd.rb != b->rb) return fail(QG_EINTERNAL, "batched plan with %d register bits", pd.rb);
+            pd.phase_begin += (int)phases.size();
+        }
+        for (PhaseDesc &ph : prog.phases) {
+            ph.op_begin += (int)ops.size();
+            ph.op_end += (int)ops.size();
+        }
+        bc[c].n = q.n_qubits;
+        bc[c].pass_begin = (int)passes.size();
+        bc[c].n_pass = (int)prog.passes.size();
+        bc[c].obs_begin = obs_off ? (int32_t)obs_off[c] : 0;
+        bc[c].obs_count = obs_off ? (int32_t)(obs_off[c + 1] - obs_off[c]) : 0;
+        const bool one_tile = bc[c].n_pass == 1 && prog.passes[0].n_tiles == 1;
+        cost[c] = one_tile ? (double)(1ull << q.n_qubits) * (1 + q.n_gates) * 1e-3
+                           : (double)(1ull << q.n_qubits) * (bc[c].n_pass + 2);
+        if (!one_tile) {
+            n_big = std::max(n_big, q.n_qubits);
+            n_big_count++;
+        }
+        passes.insert(passes.end(), prog.passes.begin(), prog.passes.end());
+        phases.insert(phases.end(), prog.phases.begin(), prog.phases.end());
+        ops.insert(ops.end(), prog.ops.begin(), prog.ops.end());
+        b->shape.push_back({q.n_qubits, q.n_gates, b->gate_rows.size()});
+        b->gate_rows.insert(b->gate_rows.end(), q.gate_type, q.gate_type + 3 * q.n_gates);
+    }
+    std::vector<int32_t> order(nc);
+    for (int c = 0; c < nc; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+
+    Pack pk;
+    const size_t o_circ = pk.add(bc);
+    const size_t o_order = pk.add(order);
+    const size_t o_pass = pk.add(passes);
+    const size_t o_phase = pk.add(phases);
+    const size_t o_ops = pk.add(ops);
+    const int64_t n_terms = obs_off ? obs_off[nc] : 0;
+    const size_t o_mask = pk.add(zmask, n_terms * sizeof(uint64_t));
+    const size_t o_coef = pk.add(coeff, n_terms * sizeof(double));
+    const int zero = 0;
+    const size_t o_cnt = pk.add(&zero, sizeof zero);
+    hipStream_t st = b->cx.stream;
+    HIP_TRY(b->dev.buf.ensure(pk.bytes.size(), st), "batch tables");
+    b->dev.off_ops = o_ops;
+    HIP_TRY(hipMemcpyAsync(b->dev.buf.p, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice, st), "upload batch");
+    HIP_TRY(hipStreamSynchronize(st), "upload batch");
+    unsigned char *base = static_cast<unsigned char *>(b->dev.buf.p);
+
+    int dev_id = 0, n_cu = 256;
+    (void)hipGetDevice(&dev_id);
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev_id);
+    const int per_cu = 2;
+    int grid = std::max(1, std::min(nc, n_cu * per_cu));
+    const size_t amp = b->c64 ? 8 : 16;
+    uint64_t stride = n_big > 0 ? (1ull << n_big) : 0;
+    if (stride) {
+        // Only as many workgroups as can hold a multi-tile state in flight need a slot.
+        HIP_TRY(b->scratch.ensure((size_t)grid * stride * amp, st), "batch scratch");
+    }
+    BatchLaunch &L = b->L;
+    L.circs = reinterpret_cast<const BatchCirc *>(base + o_circ);
+    L.order = reinterpret_cast<const int32_t *>(base + o_order);
+    L.n_circ = nc;
+    L.passes = reinterpret_cast<const PassDesc *>(base + o_pass);
+    L.phases = reinterpret_cast<const PhaseDesc *>(base + o_phase);
+    L.ops = reinterpret_cast<const DevOp *>(base + o_ops);
+    L.masks = reinterpret_cast<const uint64_t *>(base + o_mask);
+    L.coeff = reinterpret_cast<const double *>(base + o_coef);
+    L.obs_kind = b->obs_kind;
+    L.counter = reinterpret_cast<int *>(base + o_cnt);
+    L.scratch = b->scratch.p;
+    L.scratch_stride = stride;
+    L.out = b->out;
+    L.grid = grid;
+    L.tile_bits = tile_bits;
+    b->host_ops.swap(ops);
+    *n_big_out = n_big;
+    (void)n_big_count;
+
+    // Capture reset + persistent kernel once; later launches replay the graph.
+    if (st != nullptr && nc > 0) {
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            hipError_t e1 = launch_batch(b->c64, b->rb, L, st);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(st, &g);
+            if (e1 == hipSuccess && e2 == hipSuccess && g) {
+                if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) == hipSuccess) {
+                    b->graph = g;
+                } else {
+                    b->exec = nullptr;
+                    (void)hipGraphDestroy(g);
+                }
+            } else if (g) {
+                (void)hipGraphDestroy(g);
+            }
+            (void)hipGetLastError();
+        }
+    }
+    return QG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *qg_last_error(void) { return g_err.c_str(); }
 
 const char *qg_version(void) { return "qgear-mi355x 0.1 (gfx950)"; }
+
+qg_status qg_set_tuning(const char *key, int64_t value) {
+    if (!key) return fail(QG_EINVAL, "key is NULL");
+    if (set_tuning(key, value) != 0) return fail(QG_EINVAL, "unknown tuning key or value out of range: %s = %lld", key, (long long)value);
+    return QG_OK;
+}
+
+qg_status qg_get_tuning(const char *key, int64_t *value) {
+    if (!key || !value) return fail(QG_EINVAL, "key or value is NULL");
+    if (get_tuning(key, value) != 0) return fail(QG_EINVAL, "unknown tuning key: %s", key);
+    return QG_OK;
+}
 
 qg_status qg_state_alloc(int n_qubits, qg_dtype dtype, void *dev_buf, size_t buf_bytes, void *hip_stream,
                          qg_state **out) {
@@ -431,9 +670,9 @@ qg_status qg_adjoint_grad(const qg_circuit *c, qg_dtype dtype, const uint64_t *z
         }
     } release2{obs, cx.stream};
     {
-        HIP_TRY(cx.push(pk, &dev), "upload observable");
         HIP_TRY(obs.ensure(pk.bytes.size() + 1, cx.stream), "observable buffer");
-        HIP_TRY(hipMemcpyAsync(obs.p, dev, pk.bytes.size(), hipMemcpyDeviceToDevice, cx.stream), "copy observable");
+        HIP_TRY(hipMemcpyAsync(obs.p, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice, cx.stream),
+                "upload observable");
         dev = static_cast<unsigned char *>(obs.p);
     }
     const uint64_t *dmask = reinterpret_cast<const uint64_t *>(dev + mo);
@@ -450,6 +689,7 @@ qg_status qg_adjoint_grad(const qg_circuit *c, qg_dtype dtype, const uint64_t *z
     // Reverse sweep with gradient partials
     PlanConfig rcfg = fcfg;
     rcfg.reverse = true;
+    clamp_config(&rcfg);
     std::vector<Gate> rg = execution_order(g, true);
     Program rev = build_program(rg, fuse(rg, rcfg), rcfg);
     const int n_rows = (int)rev.grad_row_slot.size();
@@ -469,11 +709,108 @@ qg_status qg_adjoint_grad(const qg_circuit *c, qg_dtype dtype, const uint64_t *z
     return QG_OK;
 }
 
+qg_status qg_batch_create(const qg_circuit *circs, int n_circ, qg_dtype dtype, int obs_kind, const int64_t *obs_off,
+                          const uint64_t *zmask, const double *coeff, void *hip_stream, double *out,
+                          qg_batch **handle) {
+    if (!handle) return fail(QG_EINVAL, "handle is NULL");
+    *handle = nullptr;
+    if (dtype != QG_C64 && dtype != QG_C128) return fail(QG_EINVAL, "unknown dtype %d", (int)dtype);
+    if (n_circ < 0) return fail(QG_EINVAL, "n_circ < 0");
+    if (n_circ > 0 && (!circs || !out)) return fail(QG_EINVAL, "circs or out is NULL");
+    if (obs_kind != QG_OBS_ZZ_CHAIN && obs_kind != QG_OBS_CSR) return fail(QG_EINVAL, "unknown obs_kind %d", obs_kind);
+    std::string err;
+    int n_big = 0;
+    for (int c = 0; c < n_circ; ++c) {
+        if (validate_circuit(&circs[c], -1, &err) != QG_OK)
+            return fail(QG_EINVAL, "circuit %d: %s", c, err.c_str());
+        if (circs[c].n_qubits > kBatchMaxQubits)
+            return fail(QG_EINVAL, "circuit %d has %d qubits; the batched form takes at most %d", c,
+                        circs[c].n_qubits, kBatchMaxQubits);
+    }
+    if (obs_kind == QG_OBS_CSR) {
+        if (!obs_off) return fail(QG_EINVAL, "obs_off is NULL");
+        if (obs_off[0] != 0) return fail(QG_EINVAL, "obs_off[0] must be 0");
+        for (int c = 0; c < n_circ; ++c) {
+            if (obs_off[c + 1] < obs_off[c]) return fail(QG_EINVAL, "obs_off is not non-decreasing at %d", c);
+            qg_status st = check_masks(zmask + obs_off[c], (int)(obs_off[c + 1] - obs_off[c]), circs[c].n_qubits);
+            if (st != QG_OK) return st;
+        }
+        if (obs_off[n_circ] > 0 && !coeff) return fail(QG_EINVAL, "coeff is NULL");
+    }
+    qg_batch *b = new (std::nothrow) qg_batch;
+    if (!b) return fail(QG_ENOMEM, "host allocation failed");
+    b->c64 = dtype == QG_C64;
+    b->n_circ = n_circ;
+    b->obs_kind = obs_kind;
+    b->out = out;
+    b->cx.stream = static_cast<hipStream_t>(hip_stream);
+    qg_status st = batch_build(b, circs, obs_off, zmask, coeff, &n_big);
+    if (st != QG_OK) {
+        delete b;
+        return st;
+    }
+    *handle = b;
+    return QG_OK;
+}
+
+qg_status qg_batch_set_params(qg_batch *b, const qg_circuit *circs) {
+    if (!b) return fail(QG_EINVAL, "batch is NULL");
+    if (b->n_circ > 0 && !circs) return fail(QG_EINVAL, "circs is NULL");
+    std::string err;
+    std::vector<DevOp> ops;
+    ops.reserve(b->host_ops.size());
+    for (int c = 0; c < b->n_circ; ++c) {
+        if (validate_circuit(&circs[c], -1, &err) != QG_OK)
+            return fail(QG_EINVAL, "circuit %d: %s", c, err.c_str());
+        if (circs[c].n_qubits != b->shape[c].n || circs[c].n_gates != b->shape[c].g)
+            return fail(QG_EINVAL, "circuit %d does not match the batch's structure", c);
+        for (int g = 0; g < circs[c].n_gates; ++g)
+            for (int k = 0; k < 3; ++k)
+                if (circs[c].gate_type[3 * g + k] != b->gate_rows[b->shape[c].row0 + 3 * g + k])
+                    return fail(QG_EINVAL, "circuit %d gate %d differs from the batch's structure", c, g);
+        Program prog = plan_batch_circuit(circs[c], b->c64);
+        ops.insert(ops.end(), prog.ops.begin(), prog.ops.end());
+    }
+    if (ops.size() != b->host_ops.size()) return fail(QG_EINTERNAL, "re-planned op count differs");
+    b->host_ops.swap(ops);
+    if (!b->host_ops.empty()) {
+        HIP_TRY(b->ops_stage.ready(b->host_ops.size() * sizeof(DevOp)), "staging");
+        std::memcpy(b->ops_stage.h, b->host_ops.data(), b->host_ops.size() * sizeof(DevOp));
+        HIP_TRY(hipMemcpyAsync(b->dev.p_ops(), b->ops_stage.h, b->host_ops.size() * sizeof(DevOp),
+                               hipMemcpyHostToDevice, b->cx.stream),
+                "upload ops");
+        HIP_TRY(hipEventRecord(b->ops_stage.ev, b->cx.stream), "event");
+        b->ops_stage.pending = true;
+    }
+    return QG_OK;
+}
+
+qg_status qg_batch_launch(qg_batch *b) {
+    if (!b) return fail(QG_EINVAL, "batch is NULL");
+    if (b->n_circ == 0) return QG_OK;
+    if (b->exec) {
+        HIP_TRY(hipGraphLaunch(b->exec, b->cx.stream), "graph launch");
+        return QG_OK;
+    }
+    HIP_TRY(launch_batch(b->c64, b->rb, b->L, b->cx.stream), "batched kernel");
+    return QG_OK;
+}
+
+qg_status qg_batch_free(qg_batch *b) {
+    if (!b) return QG_OK;
+    (void)hipStreamSynchronize(b->cx.stream);
+    delete b;
+    return QG_OK;
+}
+
 qg_status qg_batch_expval(const qg_circuit *circs, int n_circ, qg_dtype dtype, int obs_kind, const int64_t *obs_off,
                           const uint64_t *zmask, const double *coeff, void *hip_stream, double *out) {
-    (void)circs; (void)n_circ; (void)dtype; (void)obs_kind; (void)obs_off; (void)zmask; (void)coeff;
-    (void)hip_stream; (void)out;
-    return fail(QG_EUNSUPPORTED, "qg_batch_expval is not built yet");
+    qg_batch *b = nullptr;
+    qg_status st = qg_batch_create(circs, n_circ, dtype, obs_kind, obs_off, zmask, coeff, hip_stream, out, &b);
+    if (st != QG_OK) return st;
+    st = qg_batch_launch(b);
+    qg_status st2 = qg_batch_free(b);
+    return st != QG_OK ? st : st2;
 }
 
 }  // extern "C"

@@ -60,6 +60,32 @@ struct PassDesc {
     int32_t grad_base;   // first gradient row written by this pass (adjoint sweeps)
     int32_t n_grad;      // gradient rows written by this pass
     uint64_t n_tiles;    // active tiles = launch size
+    int32_t flags;       // PASS_* bits
+    int32_t swz_bits;    // block index: XOR the low swz_bits bits with the next ones
+};
+
+enum PassFlags : int32_t {
+    PASS_NT = 1,  // non-temporal loads and stores of the state (streaming, no reuse)
+};
+
+// One circuit of a batched launch: its passes are passes[pass_begin, +n_pass);
+// its observable terms (QG_OBS_CSR) are masks/coeff[obs_begin, +obs_count).
+struct BatchCirc {
+    int32_t n;
+    int32_t pass_begin;
+    int32_t n_pass;
+    int32_t obs_begin;
+    int32_t obs_count;
+    int32_t pad;
+};
+
+// A small pass passed by value as the kernel argument (no upload on the stream).
+constexpr int kInlinePhases = 2;
+constexpr int kInlineOps = 12;
+struct InlineProg {
+    PassDesc pass;   // phase_begin = 0
+    PhaseDesc phases[kInlinePhases];
+    DevOp ops[kInlineOps];
 };
 
 }  // namespace qg

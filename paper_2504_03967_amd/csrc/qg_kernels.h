@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/qg.h"
 #include "qg_internal.h"
 
 namespace qg {
@@ -11,9 +12,11 @@ namespace qg {
 // at the given byte offsets; `host_pass` is the same pass on the host (launch
 // shape).  ns = 1 (psi only) or 2 (psi and lam, adjoint sweep with gradient
 // partials gpart[row * gstride + tile * waves + wave]).
-hipError_t launch_tile(bool c64, const PassDesc &host_pass, const void *dev, size_t pass_off,
-                       size_t phase_off, size_t op_off, int pass_idx, int ns, void *psi,
-                       void *lam, double *gpart, int64_t gstride, hipStream_t st);
+// When `inl` is not NULL the pass travels by value as the kernel argument and
+// `dev` is not read.
+hipError_t launch_tile(bool c64, const PassDesc &host_pass, const InlineProg *inl, const void *dev,
+                       size_t pass_off, size_t phase_off, size_t op_off, int pass_idx, int ns,
+                       void *psi, void *lam, double *gpart, int64_t gstride, hipStream_t st);
 
 // psi <- |0...0>
 hipError_t launch_zero_state(bool c64, void *psi, uint64_t dim, hipStream_t st);
@@ -46,6 +49,24 @@ hipError_t launch_grad_rows(const double *gpart, int64_t gstride, int64_t count,
 hipError_t launch_grad_slots(const double *rows, const int32_t *row_slot, int n_rows, double *grad,
                              int n_params, hipStream_t st);
 
-hipError_t set_kernel_attributes();
+// Batched persistent launch (all pointers are device pointers).
+struct BatchLaunch {
+    const BatchCirc *circs;
+    const int32_t *order;       // longest-first processing order
+    int n_circ;
+    const PassDesc *passes;
+    const PhaseDesc *phases;
+    const DevOp *ops;
+    const uint64_t *masks;
+    const double *coeff;
+    int obs_kind;
+    int *counter;               // work counter (reset by the launch)
+    void *scratch;              // grid * scratch_stride amplitudes for multi-tile circuits
+    uint64_t scratch_stride;    // amplitudes per workgroup slot
+    double *out;
+    int grid;
+    int tile_bits;
+};
+hipError_t launch_batch(bool c64, int rb, const BatchLaunch &L, hipStream_t st);
 
 }  // namespace qg

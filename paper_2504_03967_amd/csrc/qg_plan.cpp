@@ -125,23 +125,76 @@ int needs_register(const Item &it) {
 
 }  // namespace
 
+Tuning &tuning() {
+    static Tuning t;
+    return t;
+}
+
+namespace {
+struct Knob {
+    const char *name;
+    int *(*field)(Tuning &);
+    int lo, hi;
+};
+const Knob kKnobs[] = {
+    {"tile_bits_c128", [](Tuning &t) { return &t.tile_bits[0]; }, 2, 13},
+    {"tile_bits_c64", [](Tuning &t) { return &t.tile_bits[1]; }, 2, 14},
+    {"reg_bits_c128", [](Tuning &t) { return &t.reg_bits[0]; }, 1, 4},
+    {"reg_bits_c64", [](Tuning &t) { return &t.reg_bits[1]; }, 1, 5},
+    {"low_bits_c128", [](Tuning &t) { return &t.low_bits[0]; }, 0, 13},
+    {"low_bits_c64", [](Tuning &t) { return &t.low_bits[1]; }, 0, 14},
+    {"max_high_c128", [](Tuning &t) { return &t.max_high[0]; }, 1, 13},
+    {"max_high_c64", [](Tuning &t) { return &t.max_high[1]; }, 1, 14},
+    {"nt", [](Tuning &t) { return &t.nt; }, 0, 1},
+    {"swz_bits", [](Tuning &t) { return &t.swz_bits; }, 0, 16},
+};
+}  // namespace
+
+int set_tuning(const char *key, int64_t value) {
+    for (const Knob &k : kKnobs) {
+        if (std::strcmp(k.name, key) == 0) {
+            if (value < k.lo || value > k.hi) return -1;
+            *k.field(tuning()) = (int)value;
+            return 0;
+        }
+    }
+    return -1;
+}
+
+int get_tuning(const char *key, int64_t *value) {
+    for (const Knob &k : kKnobs) {
+        if (std::strcmp(k.name, key) == 0) {
+            *value = *k.field(tuning());
+            return 0;
+        }
+    }
+    return -1;
+}
+
 PlanConfig default_config(int n, bool c64, int fusion) {
+    const Tuning &t = tuning();
+    const int d = c64 ? 1 : 0;
     PlanConfig c;
     c.n = n;
     c.c64 = c64;
     c.fusion = fusion;
-    if (c64) {
-        c.tile_bits = 13;
-        c.reg_bits = 5;
-        c.low_bits = 8;
-        c.max_high = 5;
-    } else {
-        c.tile_bits = 12;
-        c.reg_bits = 4;
-        c.low_bits = 7;
-        c.max_high = 5;
-    }
+    c.tile_bits = t.tile_bits[d];
+    c.reg_bits = t.reg_bits[d];
+    c.low_bits = std::min(t.low_bits[d], c.tile_bits);
+    c.max_high = std::max(1, std::min(t.max_high[d], c.tile_bits - c.low_bits));
+    c.flags = t.nt ? PASS_NT : 0;
+    c.swz_bits = t.swz_bits;
     return c;
+}
+
+void clamp_config(PlanConfig *c) {
+    // Two complex128 states of 2^5 amplitudes per thread exceed the register file.
+    if (c->reverse && !c->c64) {
+        c->tile_bits = std::min(c->tile_bits, 12);
+        c->reg_bits = std::min(c->reg_bits, 4);
+    }
+    c->low_bits = std::min(c->low_bits, c->tile_bits);
+    c->max_high = std::max(1, std::min(c->max_high, c->tile_bits - c->low_bits));
 }
 
 void gate_matrix(int op, const double *p, cd m[2][2]) {
@@ -255,7 +308,7 @@ std::vector<PassRange> fuse(const std::vector<Gate> &g, const PlanConfig &cfg) {
     const int low = n <= b ? n : std::min(cfg.low_bits, b);
     const uint64_t low_mask = low >= 64 ? ~0ull : ((1ull << low) - 1);
     const int max_high = n <= b ? 64 : std::min(cfg.max_high, b - low);
-    const int kMaxGatesPerPass = 4096;
+    const int kMaxGatesPerPass = cfg.max_gates_per_pass;
     const int kMaxGradPerPass = 64;  // bounds the adjoint partial-sum scratch
     int begin = 0, grads = 0;
     uint64_t high = 0;
@@ -330,6 +383,7 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
         pd.tb = tb;
         pd.fixed_mask = fixed;
         pd.fixed_val = fixed;
+        pd.flags = cfg.flags;
         int free_bits = 0;
         for (int q = 0; q < n; ++q) {
             if ((tile >> q & 1) || (fixed >> q & 1)) continue;
@@ -343,6 +397,7 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
             free_bits++;
         }
         pd.n_tiles = 1ull << free_bits;
+        pd.swz_bits = std::min(cfg.swz_bits, free_bits / 2);
         pd.phase_begin = (int)prog.phases.size();
 
         // ---- phases: register positions must hold every mixing op's target

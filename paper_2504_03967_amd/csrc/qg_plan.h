@@ -27,9 +27,29 @@ struct PlanConfig {
     int max_high = 5;     // fused pass: distinct required qubits >= low_bits
     int fusion = QG_FUSE_GREEDY;
     bool reverse = false; // adjoint sweep: reversed gates, daggered, with gradient ops
+    int flags = 0;        // PASS_* bits for every pass
+    int swz_bits = 0;     // tile-order swizzle of the block index
+    int max_gates_per_pass = 4096;
 };
 
+// Process-wide tuning of the planner (defaults measured on MI355X; set by
+// qg_set_tuning or the autotuner).
+struct Tuning {
+    int tile_bits[2] = {12, 13};  // [c128, c64]
+    int reg_bits[2] = {4, 5};
+    int low_bits[2] = {7, 8};
+    int max_high[2] = {5, 5};
+    int nt = 1;
+    int swz_bits = 0;
+};
+Tuning &tuning();
+// Returns 0 on success, -1 for an unknown key or out-of-range value.
+int set_tuning(const char *key, int64_t value);
+int get_tuning(const char *key, int64_t *value);
+
 PlanConfig default_config(int n, bool c64, int fusion);
+// Re-establishes the invariants between knobs after a field was changed.
+void clamp_config(PlanConfig *c);
 
 // One fused pass as a gate range [g_begin, g_end) in execution order.
 struct PassRange {

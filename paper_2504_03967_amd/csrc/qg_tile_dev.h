@@ -1,0 +1,406 @@
+// qg_tile_dev.h -- device-side pieces of a tile pass, shared by the pass kernel
+// (one tile per workgroup) and the batched persistent kernel (whole circuits per
+// workgroup).  See qg_internal.h for the program format.
+//
+// Thread `tid` holds amplitudes a[s][e], e in [0, 2^RB), of state s (psi, and
+// lambda in adjoint sweeps) at tile position tp(tid) | ep(e); global index
+// gbase(tile) | tg(tid) | eg(e).  In a batched launch a workgroup may have more
+// threads than the tile needs; threads with tid >= 2^tb are inactive: they
+// take part in barriers only.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "qg_internal.h"
+
+namespace qg {
+namespace dev {
+
+template <typename R> struct V2;
+template <> struct V2<double> { using T = double2; };
+template <> struct V2<float> { using T = float2; };
+
+// LDS slot of tile position p: XOR-swizzle the low bits of a 256-byte bank row
+// with the next bits so that strided register layouts spread over the banks.
+template <typename R>
+__device__ __forceinline__ uint32_t swz(uint32_t p) {
+    constexpr uint32_t S = sizeof(R) == 8 ? 4 : 5;
+    return p ^ ((p >> S) & ((1u << S) - 1));
+}
+
+template <typename C, typename R>
+__device__ __forceinline__ void mat2(const R (&m)[8], C v0, C v1, C &o0, C &o1) {
+    o0.x = m[0] * v0.x - m[1] * v0.y + m[2] * v1.x - m[3] * v1.y;
+    o0.y = m[0] * v0.y + m[1] * v0.x + m[2] * v1.y + m[3] * v1.x;
+    o1.x = m[4] * v0.x - m[5] * v0.y + m[6] * v1.x - m[7] * v1.y;
+    o1.y = m[4] * v0.y + m[5] * v0.x + m[6] * v1.y + m[7] * v1.x;
+}
+
+template <typename C, typename R>
+__device__ __forceinline__ C cmul(C v, R re, R im) {
+    C o;
+    o.x = v.x * re - v.y * im;
+    o.y = v.x * im + v.y * re;
+    return o;
+}
+
+__device__ __forceinline__ double wave_sum(double v, int width) {
+    for (int off = width >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, width);
+    return v;
+}
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double2 ld_nt(const double2 *p) {
+    const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
+    double2 r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+__device__ __forceinline__ float2 ld_nt(const float2 *p) {
+    const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(p));
+    float2 r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+__device__ __forceinline__ void st_nt(double2 *p, double2 a) {
+    d2v v;
+    v.x = a.x;
+    v.y = a.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<d2v *>(p));
+}
+__device__ __forceinline__ void st_nt(float2 *p, float2 a) {
+    f2v v;
+    v.x = a.x;
+    v.y = a.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<f2v *>(p));
+}
+
+// Index bit of a qubit reference: a tile position (bit of the amplitude's
+// tile position) or a qubit outside the tile (constant over the tile).
+struct Bit {
+    uint32_t mask;
+    bool fixed_one;
+    __device__ __forceinline__ bool of(uint32_t pos) const { return mask ? (pos & mask) != 0 : fixed_one; }
+};
+
+__device__ __forceinline__ Bit make_bit(int ref, uint64_t gbase) {
+    Bit b;
+    b.mask = ref >= 0 ? (1u << ref) : 0u;
+    b.fixed_one = ref < 0 && ((gbase >> (-1 - ref)) & 1ull);
+    return b;
+}
+
+// Component-wise select (a select of whole 16-byte vectors can become a select
+// of their addresses, which forces the register arrays into scratch memory).
+template <typename C>
+__device__ __forceinline__ C sel(bool c, C x, C y) {
+    C o;
+    o.x = c ? x.x : y.x;
+    o.y = c ? x.y : y.y;
+    return o;
+}
+
+// Im(conj(l) * p)
+template <typename C>
+__device__ __forceinline__ double im_conj_mul(C l, C p) {
+    return (double)l.x * p.y - (double)l.y * p.x;
+}
+
+template <int J, int NS, int NR, typename C, typename R>
+__device__ __forceinline__ void apply_mat(C (&a)[NS][NR], const R (&m)[8]) {
+    constexpr int jb = 1 << J;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int e = 0; e < NR; ++e) {
+            if (e & jb) continue;
+            const C v0 = a[s][e], v1 = a[s][e | jb];
+            mat2(m, v0, v1, a[s][e], a[s][e | jb]);
+        }
+}
+
+template <int J, int NS, int NR, typename C, typename R>
+__device__ __forceinline__ void apply_cmat(C (&a)[NS][NR], const R (&m)[8], uint32_t tp, const uint32_t (&ep)[NR],
+                                           int cref) {
+    constexpr int jb = 1 << J;
+    const uint32_t cm = cref >= 0 ? (1u << cref) : 0u;
+#pragma unroll
+    for (int e = 0; e < NR; ++e) {
+        if (e & jb) continue;
+        const bool on = cm == 0u || ((tp | ep[e]) & cm) != 0u;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            C o0, o1;
+            mat2(m, a[s][e], a[s][e | jb], o0, o1);
+            a[s][e] = sel(on, o0, a[s][e]);
+            a[s][e | jb] = sel(on, o1, a[s][e | jb]);
+        }
+    }
+}
+
+// sum_e Im(conj(lam_e) (P psi)_e) for P = X or Y on register slot J.
+template <int J, int NS, int NR, typename C>
+__device__ __forceinline__ double grad_xy(const C (&a)[NS][NR], bool isy) {
+    constexpr int jb = 1 << J;
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < NR; ++e) {
+        const C l = a[NS - 1][e], q = a[0][e ^ jb];
+        if (isy) {
+            const double v = (double)l.x * q.x + (double)l.y * q.y;
+            acc += (e & jb) ? v : -v;
+        } else {
+            acc += im_conj_mul(l, q);
+        }
+    }
+    return acc;
+}
+
+
+// Global index bits of tile w: deposit w into the free runs (after the optional swizzle).
+__device__ __forceinline__ uint64_t tile_gbase(const PassDesc &P, uint64_t w) {
+    uint64_t gbase = P.fixed_val;
+    if (P.swz_bits > 0) {
+        // Neighbouring blocks take tiles whose addresses differ in higher bits.
+        const uint64_t m = (1ull << P.swz_bits) - 1;
+        w ^= (w >> P.swz_bits) & m;
+    }
+    for (int r = 0; r < P.n_runs; ++r) {
+        const int len = P.run_len[r];
+        gbase |= (w & ((1ull << len) - 1)) << P.run_start[r];
+        w >>= len;
+    }
+    return gbase;
+}
+
+__device__ __forceinline__ uint64_t thread_goff(const PhaseDesc &ph, int tb, int tid) {
+    uint64_t tg = 0;
+    for (int k = 0; k < tb; ++k)
+        if ((tid >> k) & 1) tg |= ph.thr_goff[k];
+    return tg;
+}
+
+__device__ __forceinline__ uint32_t thread_poff(const PhaseDesc &ph, int tb, int tid) {
+    uint32_t tp = 0;
+    for (int k = 0; k < tb; ++k)
+        if ((tid >> k) & 1) tp |= ph.thr_poff[k];
+    return tp;
+}
+
+template <int RB>
+__device__ __forceinline__ uint64_t elem_goff(const PhaseDesc &ph, int e) {
+    uint64_t eg = 0;
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+        if ((e >> j) & 1) eg |= ph.reg_goff[j];
+    return eg;
+}
+
+template <int RB>
+__device__ __forceinline__ uint32_t elem_poff(const PhaseDesc &ph, int e) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+        if ((e >> j) & 1) v |= ph.reg_poff[j];
+    return v;
+}
+
+template <typename R, int RB, int NS>
+__device__ __forceinline__ void tile_load(const PassDesc &P, const PhaseDesc &ph, uint64_t gbase,
+                                          typename V2<R>::T *const (&st)[2],
+                                          typename V2<R>::T (&a)[NS][1 << RB], int tid) {
+    const bool nt = (P.flags & PASS_NT) != 0;
+    const uint64_t tg = thread_goff(ph, P.tb, tid);
+#pragma unroll
+    for (int e = 0; e < (1 << RB); ++e) {
+        const uint64_t off = gbase | tg | elem_goff<RB>(ph, e);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a[s][e] = nt ? ld_nt(st[s] + off) : st[s][off];
+    }
+}
+
+template <typename R, int RB, int NS>
+__device__ __forceinline__ void tile_store(const PassDesc &P, const PhaseDesc &ph, uint64_t gbase,
+                                           typename V2<R>::T *const (&st)[2],
+                                           const typename V2<R>::T (&a)[NS][1 << RB], int tid) {
+    const bool nt = (P.flags & PASS_NT) != 0;
+    const uint64_t tg = thread_goff(ph, P.tb, tid);
+#pragma unroll
+    for (int e = 0; e < (1 << RB); ++e) {
+        const uint64_t off = gbase | tg | elem_goff<RB>(ph, e);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (nt) st_nt(st[s] + off, a[s][e]);
+            else st[s][off] = a[s][e];
+        }
+    }
+}
+
+// |0...0> restricted to this tile.
+template <typename R, int RB>
+__device__ __forceinline__ void tile_zero(const PassDesc &P, const PhaseDesc &ph, uint64_t gbase,
+                                          typename V2<R>::T (&a)[1][1 << RB], int tid) {
+    const uint64_t tg = thread_goff(ph, P.tb, tid);
+#pragma unroll
+    for (int e = 0; e < (1 << RB); ++e) {
+        a[0][e].x = (gbase | tg | elem_goff<RB>(ph, e)) == 0 ? (R)1 : (R)0;
+        a[0][e].y = (R)0;
+    }
+}
+
+// sum_e |a_e|^2 (sum_{q < n-1} Z_q Z_{q+1})(index of a_e): the open-chain ZZ
+// observable, (n-1) - 2 popcount((i ^ (i >> 1)) & (2^(n-1) - 1)).
+template <typename R, int RB>
+__device__ __forceinline__ double tile_obs_zz_chain(const PassDesc &P, const PhaseDesc &ph, uint64_t gbase,
+                                                    const typename V2<R>::T (&a)[1][1 << RB], int tid, int n) {
+    const uint64_t tg = thread_goff(ph, P.tb, tid);
+    const uint64_t mask = n >= 2 ? ((1ull << (n - 1)) - 1) : 0;
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < (1 << RB); ++e) {
+        const uint64_t i = gbase | tg | elem_goff<RB>(ph, e);
+        const double p = (double)a[0][e].x * a[0][e].x + (double)a[0][e].y * a[0][e].y;
+        acc += p * (double)((n - 1) - 2 * __popcll((i ^ (i >> 1)) & mask));
+    }
+    return acc;
+}
+
+// sum_e |a_e|^2 sum_t coeff_t (-1)^{popcount(i & mask_t)}
+template <typename R, int RB>
+__device__ __forceinline__ double tile_obs_terms(const PassDesc &P, const PhaseDesc &ph, uint64_t gbase,
+                                                 const typename V2<R>::T (&a)[1][1 << RB], int tid,
+                                                 const uint64_t *__restrict__ masks, const double *__restrict__ coeff,
+                                                 int n_terms) {
+    const uint64_t tg = thread_goff(ph, P.tb, tid);
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < (1 << RB); ++e) {
+        const uint64_t i = gbase | tg | elem_goff<RB>(ph, e);
+        const double p = (double)a[0][e].x * a[0][e].x + (double)a[0][e].y * a[0][e].y;
+        double o = 0.0;
+        for (int t = 0; t < n_terms; ++t) o += (__popcll(i & masks[t]) & 1) ? -coeff[t] : coeff[t];
+        acc += p * o;
+    }
+    return acc;
+}
+
+// Runs every phase of a pass on the registers: LDS exchanges between layouts,
+// then the phase's ops.  `active` is false for threads beyond the tile's 2^tb.
+template <typename R, int RB, int NS>
+__device__ __forceinline__ void tile_phases(const PassDesc &P, const PhaseDesc *__restrict__ phases,
+                                            const DevOp *__restrict__ ops, uint64_t gbase,
+                                            typename V2<R>::T (&a)[NS][1 << RB], typename V2<R>::T *lds,
+                                            double *__restrict__ gpart, int64_t gstride, uint64_t tile_idx,
+                                            int tid, bool active) {
+    using C = typename V2<R>::T;
+    constexpr int NR = 1 << RB;
+    const int tb = P.tb;
+    const int n_phase = P.n_phase;
+    for (int p = 0; p < n_phase; ++p) {
+        const PhaseDesc &ph = phases[p];
+        const uint32_t tp = thread_poff(ph, tb, tid);
+        uint32_t ep[NR];
+#pragma unroll
+        for (int e = 0; e < NR; ++e) ep[e] = elem_poff<RB>(ph, e);
+        if (p > 0) {
+            // Move the tile into the new register layout through LDS.
+            const PhaseDesc &prev = phases[p - 1];
+            const uint32_t tq = thread_poff(prev, tb, tid);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                __syncthreads();
+                if (active) {
+#pragma unroll
+                    for (int e = 0; e < NR; ++e) lds[swz<R>(tq | elem_poff<RB>(prev, e))] = a[s][e];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < NR; ++e) a[s][e] = lds[swz<R>(tp | ep[e])];
+            }
+        }
+        for (int i = ph.op_begin; i < ph.op_end; ++i) {
+            const DevOp &op = ops[i];
+            R m[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) m[k] = (R)op.m[k];
+            const int kind = op.kind;
+            if (kind == OP_MAT) {
+                switch (op.a) {
+                case 0: apply_mat<0>(a, m); break;
+                case 1: if constexpr (RB > 1) apply_mat<1>(a, m); break;
+                case 2: if constexpr (RB > 2) apply_mat<2>(a, m); break;
+                case 3: if constexpr (RB > 3) apply_mat<3>(a, m); break;
+                case 4: if constexpr (RB > 4) apply_mat<4>(a, m); break;
+                }
+            } else if (kind == OP_CMAT) {
+                if (op.c < 0 && !((gbase >> (-1 - op.c)) & 1ull)) continue;
+                switch (op.a) {
+                case 0: apply_cmat<0>(a, m, tp, ep, op.c); break;
+                case 1: if constexpr (RB > 1) apply_cmat<1>(a, m, tp, ep, op.c); break;
+                case 2: if constexpr (RB > 2) apply_cmat<2>(a, m, tp, ep, op.c); break;
+                case 3: if constexpr (RB > 3) apply_cmat<3>(a, m, tp, ep, op.c); break;
+                case 4: if constexpr (RB > 4) apply_cmat<4>(a, m, tp, ep, op.c); break;
+                }
+            } else if (kind == OP_DIAG1) {
+                const Bit ba = make_bit(op.a, gbase);
+#pragma unroll
+                for (int e = 0; e < NR; ++e) {
+                    const bool one = ba.of(tp | ep[e]);
+                    const R re = one ? m[2] : m[0], im = one ? m[3] : m[1];
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) a[s][e] = cmul(a[s][e], re, im);
+                }
+            } else if (kind == OP_DIAG2) {
+                const Bit ba = make_bit(op.a, gbase), bc = make_bit(op.c, gbase);
+#pragma unroll
+                for (int e = 0; e < NR; ++e) {
+                    const bool both = ba.of(tp | ep[e]) && bc.of(tp | ep[e]);
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) a[s][e] = sel(both, cmul(a[s][e], m[0], m[1]), a[s][e]);
+                }
+            } else {
+                if constexpr (NS == 2) {
+                    double acc = 0.0;
+                    if (kind == OP_GRADZ) {
+                        const Bit ba = make_bit(op.a, gbase);
+#pragma unroll
+                        for (int e = 0; e < NR; ++e) {
+                            const double v = im_conj_mul(a[1][e], a[0][e]);
+                            acc += ba.of(tp | ep[e]) ? -v : v;
+                        }
+                    } else if (kind == OP_GRADP11) {
+                        const Bit ba = make_bit(op.a, gbase), bc = make_bit(op.c, gbase);
+#pragma unroll
+                        for (int e = 0; e < NR; ++e) {
+                            const double v = im_conj_mul(a[1][e], a[0][e]);
+                            acc += (ba.of(tp | ep[e]) && bc.of(tp | ep[e])) ? -2.0 * v : 0.0;
+                        }
+                    } else {
+                        const bool isy = kind == OP_GRADY;
+                        switch (op.a) {
+                        case 0: acc = grad_xy<0>(a, isy); break;
+                        case 1: if constexpr (RB > 1) acc = grad_xy<1>(a, isy); break;
+                        case 2: if constexpr (RB > 2) acc = grad_xy<2>(a, isy); break;
+                        case 3: if constexpr (RB > 3) acc = grad_xy<3>(a, isy); break;
+                        case 4: if constexpr (RB > 4) acc = grad_xy<4>(a, isy); break;
+                        }
+                    }
+                    const int width = blockDim.x < 64 ? (int)blockDim.x : 64;
+                    acc = wave_sum(acc, width);
+                    if ((tid & (width - 1)) == 0) {
+                        const int waves = (blockDim.x + 63) / 64;
+                        gpart[(int64_t)op.g * gstride + (int64_t)tile_idx * waves + tid / 64] = acc;
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace dev
+}  // namespace qg

@@ -24,7 +24,8 @@ OBS_ZZ_CHAIN, OBS_CSR = 0, 1
 EXPORTS = (
     "qg_state_alloc", "qg_state_free", "qg_state_reset", "qg_state_set_stream", "qg_state_info",
     "qg_apply_circuit", "qg_probs", "qg_sample", "qg_expval", "qg_adjoint_grad", "qg_batch_expval",
-    "qg_plan_passes", "qg_last_error", "qg_version",
+    "qg_plan_passes", "qg_last_error", "qg_version", "qg_set_tuning", "qg_get_tuning",
+    "qg_batch_create", "qg_batch_set_params", "qg_batch_launch", "qg_batch_free",
 )
 
 
@@ -59,6 +60,12 @@ def _load() -> ctypes.CDLL:
         "qg_adjoint_grad": [P, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, P, P, P],
         "qg_batch_expval": [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P],
         "qg_plan_passes": [P, ctypes.c_int, ctypes.c_int, P, P],
+        "qg_batch_create": [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P],
+        "qg_batch_set_params": [P, P],
+        "qg_batch_launch": [P],
+        "qg_batch_free": [P],
+        "qg_set_tuning": [ctypes.c_char_p, I64],
+        "qg_get_tuning": [ctypes.c_char_p, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -81,6 +88,16 @@ def _check(st: int) -> None:
 
 def version() -> str:
     return lib.qg_version().decode()
+
+
+def set_tuning(key: str, value: int) -> None:
+    _check(lib.qg_set_tuning(key.encode(), int(value)))
+
+
+def get_tuning(key: str) -> int:
+    v = ctypes.c_int64()
+    _check(lib.qg_get_tuning(key.encode(), ctypes.byref(v)))
+    return int(v.value)
 
 
 def _stream_handle(stream: Optional[torch.cuda.Stream]) -> ctypes.c_void_p:
@@ -191,6 +208,81 @@ def adjoint_grad(circ, masks, coeffs, n_params: int, dtype="c128", stream=None):
     return val[0], grad[:n_params]
 
 
+class _CircuitArray:
+    def __init__(self, circs):
+        self.args = [CircuitArgs(c) for c in circs]
+        self.arr = (_Circuit * max(len(circs), 1))(*[a.c for a in self.args])
+
+    @property
+    def ptr(self):
+        return ctypes.cast(self.arr, ctypes.c_void_p)
+
+
+def _obs_csr(obs):
+    """obs: None (ZZ chain) or a list of (masks, coeffs) per circuit."""
+    if obs is None:
+        return OBS_ZZ_CHAIN, None, None, None
+    off = np.zeros(len(obs) + 1, dtype=np.int64)
+    for i, (m, _) in enumerate(obs):
+        off[i + 1] = off[i] + len(m)
+    masks = np.ascontiguousarray(np.concatenate([np.asarray(m, np.uint64) for m, _ in obs]) if obs else
+                                 np.zeros(0, np.uint64), dtype=np.uint64)
+    coeffs = np.ascontiguousarray(np.concatenate([np.asarray(c, np.float64) for _, c in obs]) if obs else
+                                  np.zeros(0), dtype=np.float64)
+    return OBS_CSR, off, masks, coeffs
+
+
+class Batch:
+    """Reusable batched launch (graph-captured when the stream is not the NULL stream)."""
+
+    def __init__(self, circs, dtype="c128", obs=None, stream: Optional[torch.cuda.Stream] = None):
+        self.n = len(circs)
+        self.code = _dtype_code(dtype)
+        self.out = torch.zeros(max(self.n, 1), dtype=torch.float64, device="cuda")
+        self._ca = _CircuitArray(circs)
+        kind, off, masks, coeffs = _obs_csr(obs)
+        self._obs = (off, masks, coeffs)
+        h = ctypes.c_void_p()
+        _check(lib.qg_batch_create(self._ca.ptr, self.n, self.code, kind,
+                                   None if off is None else off.ctypes.data,
+                                   None if masks is None else masks.ctypes.data,
+                                   None if coeffs is None else coeffs.ctypes.data,
+                                   _stream_handle(stream), ctypes.c_void_p(self.out.data_ptr()), ctypes.byref(h)))
+        self.handle = h
+
+    def set_params(self, circs) -> None:
+        ca = _CircuitArray(circs)
+        _check(lib.qg_batch_set_params(self.handle, ca.ptr))
+
+    def launch(self) -> torch.Tensor:
+        _check(lib.qg_batch_launch(self.handle))
+        return self.out[:self.n]
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib.qg_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_expval(circs, dtype="c128", obs=None, stream=None) -> torch.Tensor:
+    """One-shot batched expectations (qg_batch_expval)."""
+    ca = _CircuitArray(circs)
+    kind, off, masks, coeffs = _obs_csr(obs)
+    out = torch.zeros(max(len(circs), 1), dtype=torch.float64, device="cuda")
+    _check(lib.qg_batch_expval(ca.ptr, len(circs), _dtype_code(dtype), kind,
+                               None if off is None else off.ctypes.data,
+                               None if masks is None else masks.ctypes.data,
+                               None if coeffs is None else coeffs.ctypes.data,
+                               _stream_handle(stream), ctypes.c_void_p(out.data_ptr())))
+    return out[:len(circs)]
+
+
 def plan_passes(circ, dtype="c128", fusion: int = FUSE_GREEDY):
     """(pass index of each gate, number of passes) of the library's plan (host only)."""
     ca = CircuitArgs(circ)
@@ -198,3 +290,34 @@ def plan_passes(circ, dtype="c128", fusion: int = FUSE_GREEDY):
     npass = ctypes.c_int32()
     _check(lib.qg_plan_passes(ca.ptr, _dtype_code(dtype), int(fusion), pog.ctypes.data, ctypes.byref(npass)))
     return pog[:ca.gt.shape[0]], int(npass.value)
+
+
+class QGExpval(torch.autograd.Function):
+    """f(params) = sum_m coeff_m <Z_{mask_m}> of ``circ`` with its trainable angles
+    (``circ.param_idx`` slots) taken from ``params`` (float64, one value per slot).
+
+    Forward and the gradient come from one call of the library's adjoint sweep
+    (qg_adjoint_grad) when a gradient is needed; otherwise the forward is an
+    apply + expval on a fresh state.
+    """
+
+    @staticmethod
+    def forward(ctx, params: torch.Tensor, circ, masks, coeffs, dtype: str = "c128"):
+        p = params.detach().to("cpu", torch.float64).numpy()
+        c = circ.copy()
+        sel = c.param_idx >= 0
+        c.gate_param[sel, 0] = p[c.param_idx[sel]]
+        if params.requires_grad:
+            val, grad = adjoint_grad(c, masks, coeffs, int(p.size), dtype)
+            ctx.save_for_backward(grad.to(params.device))
+            return val.to(params.device)
+        st = State(c.n_qubits, dtype)
+        st.apply(c, FUSE_GREEDY)
+        _, total = st.expval(masks, coeffs)
+        st.close()
+        return total.to(params.device)
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return g * grad, None, None, None, None

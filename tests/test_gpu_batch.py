@@ -1,0 +1,96 @@
+"""Batched persistent launch (config 4 shape) against the oracle, per circuit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2504_03967_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def qg():
+    from paper_2504_03967_amd import qg as lib
+    assert torch.cuda.is_available()
+    return lib
+
+
+def ref_zz(c):
+    psi = oracle.simulate(c)
+    return float(oracle.expval(psi, W.zz_chain_masks(c.n_qubits)).sum())
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_small_batch_all_sizes(qg, dtype):
+    circs = W.config4(seed=11, n_circuits=60, n_min=1, n_max=16, l_min=1, l_max=4)
+    out = qg.batch_expval(circs, dtype).cpu().numpy()
+    ref = np.array([ref_zz(c) for c in circs])
+    # tolerance per Z_i Z_{i+1} term, scaled by the number of terms
+    scale = np.array([max(c.n_qubits - 1, 1) for c in circs])
+    assert np.all(np.abs(out - ref) <= TOL[dtype] * scale)
+
+
+def test_config4_full_sampled(qg):
+    circs = W.config4()
+    assert len(circs) == 4096
+    for dtype in ("c128", "c64"):
+        out = qg.batch_expval(circs, dtype).cpu().numpy()
+        pick = list(range(0, 4096, 97)) + [int(np.argmax([c.n_qubits * 100 + c.n_gates for c in circs]))]
+        for i in pick:
+            assert abs(out[i] - ref_zz(circs[i])) <= TOL[dtype] * (circs[i].n_qubits - 1), (dtype, i)
+
+
+def test_graph_replays_and_new_params(qg):
+    circs = W.config4(seed=21, n_circuits=40, n_min=8, n_max=18, l_min=2, l_max=5)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = qg.Batch(circs, "c128", stream=stream)
+        eager = qg.batch_expval(circs, "c128", stream=stream).clone()
+        for rep in range(3):
+            got = b.launch().clone()
+            stream.synchronize()
+            assert torch.allclose(got, eager, atol=1e-12, rtol=0), rep
+            # eager work and a host sync between replays
+            junk = torch.randn(1000, device="cuda").sum().item()
+        # new angles, same structure
+        rng = np.random.default_rng(3)
+        new = []
+        for c in circs:
+            d = c.copy()
+            d.gate_param[:, 0] = rng.uniform(-np.pi, np.pi, d.n_gates)
+            new.append(d)
+        b.set_params(new)
+        got = b.launch().clone()
+        stream.synchronize()
+    ref = np.array([ref_zz(c) for c in new])
+    assert np.max(np.abs(got.cpu().numpy() - ref) / np.array([c.n_qubits - 1 for c in new])) < 1e-12
+    b.close()
+
+
+def test_csr_observables(qg):
+    circs = W.config4(seed=31, n_circuits=12, n_min=3, n_max=15, l_min=1, l_max=3)
+    rng = np.random.default_rng(9)
+    obs = []
+    for c in circs:
+        k = int(rng.integers(0, 5))
+        obs.append((rng.integers(0, 1 << c.n_qubits, k).astype(np.uint64), rng.normal(size=k)))
+    out = qg.batch_expval(circs, "c128", obs=obs).cpu().numpy()
+    for c, (m, w), o in zip(circs, obs, out):
+        ref = float(np.dot(w, oracle.expval(oracle.simulate(c), m))) if len(m) else 0.0
+        assert abs(o - ref) < 1e-12 * max(1, len(m))
+
+
+def test_batch_validation(qg):
+    circs = W.config4(seed=1, n_circuits=2)
+    bad = circs[0].copy()
+    bad.gate_type[0, 2] = 40
+    with pytest.raises(qg.QGError):
+        qg.batch_expval([circs[1], bad])
+    big = W.ghz(23)
+    with pytest.raises(qg.QGError):
+        qg.batch_expval([big])
+    with pytest.raises(qg.QGError):
+        qg.Batch(circs).set_params([circs[1], circs[0]])
