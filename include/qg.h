@@ -190,6 +190,50 @@ qg_status qg_batch_free(qg_batch *b);
 qg_status qg_plan_passes(const qg_circuit *c, qg_dtype dtype, int fusion_mode,
                          int32_t *pass_of_gate, int32_t *n_passes);
 
+/* ---- Learned fusion: the cost model (not in the paper; its backend fixes the
+ * fusion width at 5, App. D.2).  An MLP with three ReLU hidden layers of width
+ * 64 and a linear scalar output, FP32, run by the library's own forward,
+ * backward and Adam kernels.  Flat parameter layout: W1[n_in][64], b1[64],
+ * W2[64][64], b2[64], W3[64][64], b3[64], W4[64], b4.  x, t, y, grad and
+ * theta are host arrays; calls on a model are synchronous on its stream. */
+typedef struct qg_mlp qg_mlp;
+/* New model: He-uniform weights from SplitMix64(seed), zero biases.
+ * hidden must be 64 (QG_EUNSUPPORTED otherwise); 1 <= n_in <= 256. */
+qg_status qg_mlp_create(int n_in, int hidden, uint64_t seed, void *hip_stream, qg_mlp **out);
+qg_status qg_mlp_n_params(const qg_mlp *m, int64_t *n);
+/* Replace the parameters (and reset Adam's moments and step). */
+qg_status qg_mlp_set_params(qg_mlp *m, const float *theta);
+qg_status qg_mlp_get_params(qg_mlp *m, float *theta);
+/* y[B] for x[B][n_in]. */
+qg_status qg_mlp_forward(qg_mlp *m, const float *x, int B, float *y);
+/* Mean-squared-error loss of the batch and its gradient grad[n_params]. */
+qg_status qg_mlp_grad(qg_mlp *m, const float *x, const float *t, int B, double *loss, float *grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the given gradient. */
+qg_status qg_mlp_adam_step(qg_mlp *m, const float *grad, float lr);
+/* Minibatch Adam on N samples for `epochs` epochs (a SplitMix64(seed)
+ * Fisher-Yates shuffle per epoch, full batches only); loss_per_epoch[epochs]
+ * (host, may be NULL) receives the mean batch loss of each epoch. */
+qg_status qg_mlp_train(qg_mlp *m, const float *x, const float *t, int N, int epochs, int batch, float lr,
+                       uint64_t seed, double *loss_per_epoch);
+qg_status qg_mlp_free(qg_mlp *m);
+
+/* Number of features of a candidate pass, and the candidate fusion
+ * configurations: config k allows 4 + k required qubits outside the low
+ * block (k = 1 is the greedy default, width 5). */
+#define QG_PASS_FEATURES 24
+#define QG_PASS_CONFIGS 4
+/* Features of the whole circuit run as one pass under candidate config k
+ * (features[QG_PASS_FEATURES], host); *n_passes (may be NULL) receives the
+ * number of passes the greedy rule of that config would form. */
+qg_status qg_pass_features(const qg_circuit *c, qg_dtype dtype, int config, float *features, int32_t *n_passes);
+/* Installs the model QG_FUSE_LEARNED plans with (NULL: greedy fallback).  The
+ * learned planner prices candidate passes (each start gate, each config)
+ * with one batched forward of the model, predicting ln(pass time in
+ * microseconds), and keeps the partition of least predicted total time (dynamic
+ * programming); plans are cached per circuit structure.  The model must have
+ * QG_PASS_FEATURES inputs and stay alive while installed. */
+qg_status qg_set_cost_model(qg_mlp *m);
+
 /* Process-wide planner tuning (not part of the paper's method; performance only,
  * results are identical up to rounding for every setting).  Keys:
  *   tile_bits_c128 / tile_bits_c64   qubits per tile (amplitudes streamed per workgroup)

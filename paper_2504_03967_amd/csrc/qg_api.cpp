@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -439,6 +441,161 @@ qg_status batch_build(qg_batch *b, const qg_circuit *circs, const int64_t *obs_o
 
 }  // namespace
 
+struct qg_mlp {
+    int F = 0;
+    int P = 0;
+    hipStream_t stream = nullptr;
+    DevBuf theta, m, v, grad;
+    DevBuf act;    // z1..z3, dz1..dz3 [B][H], y, dy [B], loss slots
+    DevBuf data;   // X [N][F], T [N], order [N], Xb, Tb
+    int step = 0;
+    ~qg_mlp() {
+        theta.release();
+        m.release();
+        v.release();
+        grad.release();
+        act.release();
+        data.release();
+    }
+};
+
+namespace {
+
+struct MlpAct {
+    float *z1, *z2, *z3, *dz1, *dz2, *dz3, *y, *dy;
+    double *loss;
+};
+
+hipError_t mlp_act(qg_mlp *M, int B, int loss_slots, MlpAct *a) {
+    const size_t H = kMlpHidden;
+    const size_t need = (6 * (size_t)B * H + 2 * (size_t)B) * sizeof(float) + 256 + (size_t)(loss_slots + 1) * sizeof(double);
+    hipError_t e = M->act.ensure(need, M->stream);
+    if (e != hipSuccess) return e;
+    float *f = static_cast<float *>(M->act.p);
+    a->z1 = f; a->z2 = f + B * H; a->z3 = f + 2 * B * H;
+    a->dz1 = f + 3 * B * H; a->dz2 = f + 4 * B * H; a->dz3 = f + 5 * B * H;
+    a->y = f + 6 * B * H; a->dy = a->y + B;
+    uintptr_t lp = reinterpret_cast<uintptr_t>(a->dy + B);
+    lp = (lp + 255) & ~uintptr_t(255);
+    a->loss = reinterpret_cast<double *>(lp);
+    return hipSuccess;
+}
+
+qg_mlp *g_cost_model = nullptr;
+static_assert(kPlanFeatures == QG_PASS_FEATURES && kPlanConfigs == QG_PASS_CONFIGS, "feature layout");
+
+}  // namespace
+
+namespace {
+
+// ---- learned fusion: dynamic programming over candidate passes priced by the cost model
+
+struct PlanEntry {
+    std::vector<PassRange> ranges;
+    std::vector<int> cfg;   // candidate configuration index per pass
+};
+
+std::mutex g_plan_mu;
+std::map<uint64_t, PlanEntry> g_plan_cache;
+const qg_mlp *g_plan_cache_model = nullptr;
+
+uint64_t structure_hash(int n, bool c64, const std::vector<Gate> &g) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        h ^= v;
+        h *= 1099511628211ull;
+    };
+    mix((uint64_t)n);
+    mix(c64 ? 1 : 0);
+    for (const Gate &x : g) {
+        mix((uint64_t)(uint32_t)x.op);
+        mix((uint64_t)(uint32_t)x.q0);
+        mix((uint64_t)(uint32_t)x.q1);
+    }
+    return h;
+}
+
+qg_status learned_plan(const std::vector<Gate> &g, int n, bool c64, PlanEntry *out) {
+    const int G = (int)g.size();
+    out->ranges.clear();
+    out->cfg.clear();
+    if (!g_cost_model) {
+        PlanConfig cfg = candidate_config(n, c64, 1);
+        out->ranges = fuse(g, cfg);
+        out->cfg.assign(out->ranges.size(), 1);
+        return QG_OK;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        if (g_plan_cache_model != g_cost_model) {
+            g_plan_cache.clear();
+            g_plan_cache_model = g_cost_model;
+        }
+        auto it = g_plan_cache.find(structure_hash(n, c64, g));
+        if (it != g_plan_cache.end()) {
+            *out = it->second;
+            return QG_OK;
+        }
+    }
+    struct Cand {
+        int i, j, k;
+    };
+    std::vector<Cand> cand;
+    std::vector<float> feat;
+    PlanConfig cfgs[kPlanConfigs];
+    for (int k = 0; k < kPlanConfigs; ++k) cfgs[k] = candidate_config(n, c64, k);
+    for (int i = 0; i < G; ++i) {
+        int last_j = -1;
+        for (int k = 0; k < kPlanConfigs; ++k) {
+            const int j = first_block_end(g, i, cfgs[k]);
+            (void)last_j;
+            cand.push_back({i, j, k});
+            feat.resize(feat.size() + kPlanFeatures);
+            pass_features(g, i, j, cfgs[k], feat.data() + feat.size() - kPlanFeatures);
+            last_j = j;
+        }
+    }
+    std::vector<float> pred(cand.size());
+    qg_status st = qg_mlp_forward(g_cost_model, feat.data(), (int)cand.size(), pred.data());
+    if (st != QG_OK) return st;
+    std::vector<double> best(G + 1, 0.0);
+    std::vector<int> choice(G, -1);
+    // candidates are grouped by start i (kPlanConfigs each)
+    for (int i = G - 1; i >= 0; --i) {
+        double b = 1e300;
+        for (int k = 0; k < kPlanConfigs; ++k) {
+            const int c = i * kPlanConfigs + k;
+            const double v = std::exp((double)pred[c]) + best[cand[c].j];
+            if (v < b) {
+                b = v;
+                choice[i] = c;
+            }
+        }
+        best[i] = b;
+    }
+    for (int i = 0; i < G;) {
+        const Cand &c = cand[choice[i]];
+        out->ranges.push_back({c.i, c.j});
+        out->cfg.push_back(c.k);
+        i = c.j;
+    }
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_plan_cache[structure_hash(n, c64, g)] = *out;
+    return QG_OK;
+}
+
+Program build_learned(const std::vector<Gate> &g, const PlanEntry &e, int n, bool c64) {
+    Program prog;
+    for (size_t p = 0; p < e.ranges.size(); ++p) {
+        PlanConfig cfg = candidate_config(n, c64, e.cfg[p]);
+        std::vector<PassRange> one{e.ranges[p]};
+        append_program(&prog, build_program(g, one, cfg));
+    }
+    return prog;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *qg_last_error(void) { return g_err.c_str(); }
@@ -529,8 +686,16 @@ qg_status qg_plan_passes(const qg_circuit *c, qg_dtype dtype, int fusion_mode, i
         return fail(QG_EINVAL, "unknown fusion mode %d", fusion_mode);
     if (dtype != QG_C64 && dtype != QG_C128) return fail(QG_EINVAL, "unknown dtype %d", (int)dtype);
     std::vector<Gate> g = load_gates(c);
-    PlanConfig cfg = plan_config(c->n_qubits, dtype == QG_C64, fusion_mode);
-    std::vector<PassRange> r = fuse(g, cfg);
+    std::vector<PassRange> r;
+    if (fusion_mode == QG_FUSE_LEARNED) {
+        PlanEntry e;
+        qg_status st = learned_plan(g, c->n_qubits, dtype == QG_C64, &e);
+        if (st != QG_OK) return st;
+        r = e.ranges;
+    } else {
+        PlanConfig cfg = plan_config(c->n_qubits, dtype == QG_C64, fusion_mode);
+        r = fuse(g, cfg);
+    }
     for (size_t p = 0; p < r.size(); ++p)
         for (int i = r[p].g_begin; i < r[p].g_end; ++i)
             if (pass_of_gate) pass_of_gate[i] = (int32_t)p;
@@ -548,8 +713,16 @@ qg_status qg_apply_circuit(qg_state *s, const qg_circuit *c, int fusion_mode) {
         return fail(QG_EINVAL, "unknown fusion mode %d", fusion_mode);
     if (c->n_gates == 0) return QG_OK;
     std::vector<Gate> g = load_gates(c);
-    PlanConfig cfg = plan_config(s->n, s->c64(), fusion_mode);
-    Program prog = build_program(g, fuse(g, cfg), cfg);
+    Program prog;
+    if (fusion_mode == QG_FUSE_LEARNED) {
+        PlanEntry e;
+        qg_status st = learned_plan(g, s->n, s->c64(), &e);
+        if (st != QG_OK) return st;
+        prog = build_learned(g, e, s->n, s->c64());
+    } else {
+        PlanConfig cfg = plan_config(s->n, s->c64(), fusion_mode);
+        prog = build_program(g, fuse(g, cfg), cfg);
+    }
     return run_program(s->cx, s->c64(), prog, s->buf, nullptr, nullptr);
 }
 
@@ -811,6 +984,221 @@ qg_status qg_batch_expval(const qg_circuit *circs, int n_circ, qg_dtype dtype, i
     st = qg_batch_launch(b);
     qg_status st2 = qg_batch_free(b);
     return st != QG_OK ? st : st2;
+}
+
+
+qg_status qg_mlp_create(int n_in, int hidden, uint64_t seed, void *hip_stream, qg_mlp **out) {
+    if (!out) return fail(QG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_in < 1 || n_in > 256) return fail(QG_EINVAL, "n_in must be in [1, 256]");
+    if (hidden != kMlpHidden) return fail(QG_EUNSUPPORTED, "hidden width must be %d", kMlpHidden);
+    qg_mlp *M = new (std::nothrow) qg_mlp;
+    if (!M) return fail(QG_ENOMEM, "host allocation failed");
+    M->F = n_in;
+    M->P = mlp_param_count(n_in);
+    M->stream = static_cast<hipStream_t>(hip_stream);
+    const size_t pb = M->P * sizeof(float);
+    hipError_t e = M->theta.ensure(pb, M->stream);
+    if (e == hipSuccess) e = M->m.ensure(pb, M->stream);
+    if (e == hipSuccess) e = M->v.ensure(pb, M->stream);
+    if (e == hipSuccess) e = M->grad.ensure(pb, M->stream);
+    if (e != hipSuccess) {
+        delete M;
+        return hip_fail(e, "mlp parameters");
+    }
+    // He-uniform initial weights U(-sqrt(6/fan_in), +sqrt(6/fan_in)) from SplitMix64(seed); zero biases.
+    std::vector<float> th(M->P, 0.f);
+    uint64_t state = seed;
+    auto next = [&]() {
+        uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    };
+    const int H = kMlpHidden;
+    const int fan[4] = {n_in, H, H, H};
+    const int rows[4] = {n_in, H, H, H}, cols[4] = {H, H, H, 1};
+    size_t k = 0;
+    for (int l = 0; l < 4; ++l) {
+        const double r = std::sqrt(6.0 / fan[l]);
+        for (int i = 0; i < rows[l] * cols[l]; ++i) th[k++] = (float)((2 * next() - 1) * r);
+        k += cols[l];  // bias
+    }
+    std::vector<float> zero(M->P, 0.f);
+    e = hipMemcpy(M->theta.p, th.data(), pb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M->m.p, zero.data(), pb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M->v.p, zero.data(), pb, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        delete M;
+        return hip_fail(e, "mlp init");
+    }
+    *out = M;
+    return QG_OK;
+}
+
+qg_status qg_mlp_n_params(const qg_mlp *M, int64_t *n) {
+    if (!M || !n) return fail(QG_EINVAL, "NULL argument");
+    *n = M->P;
+    return QG_OK;
+}
+
+qg_status qg_mlp_set_params(qg_mlp *M, const float *theta) {
+    if (!M || !theta) return fail(QG_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(M->theta.p, theta, M->P * sizeof(float), hipMemcpyHostToDevice, M->stream), "set params");
+    HIP_TRY(hipMemsetAsync(M->m.p, 0, M->P * sizeof(float), M->stream), "reset adam");
+    HIP_TRY(hipMemsetAsync(M->v.p, 0, M->P * sizeof(float), M->stream), "reset adam");
+    HIP_TRY(hipStreamSynchronize(M->stream), "set params");
+    M->step = 0;
+    return QG_OK;
+}
+
+qg_status qg_mlp_get_params(qg_mlp *M, float *theta) {
+    if (!M || !theta) return fail(QG_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(theta, M->theta.p, M->P * sizeof(float), hipMemcpyDeviceToHost, M->stream), "get params");
+    HIP_TRY(hipStreamSynchronize(M->stream), "get params");
+    return QG_OK;
+}
+
+qg_status qg_mlp_forward(qg_mlp *M, const float *x, int B, float *y) {
+    if (!M || (B > 0 && (!x || !y))) return fail(QG_EINVAL, "NULL argument");
+    if (B < 0) return fail(QG_EINVAL, "B < 0");
+    if (B == 0) return QG_OK;
+    HIP_TRY(M->data.ensure((size_t)B * M->F * sizeof(float), M->stream), "mlp input");
+    HIP_TRY(hipMemcpyAsync(M->data.p, x, (size_t)B * M->F * sizeof(float), hipMemcpyHostToDevice, M->stream),
+            "mlp input");
+    MlpAct a;
+    HIP_TRY(mlp_act(M, B, 0, &a), "mlp scratch");
+    HIP_TRY(launch_mlp_forward(static_cast<float *>(M->theta.p), static_cast<float *>(M->data.p), B, M->F, a.z1, a.z2,
+                               a.z3, a.y, M->stream),
+            "mlp forward");
+    HIP_TRY(hipMemcpyAsync(y, a.y, B * sizeof(float), hipMemcpyDeviceToHost, M->stream), "mlp output");
+    HIP_TRY(hipStreamSynchronize(M->stream), "mlp forward");
+    return QG_OK;
+}
+
+qg_status qg_mlp_grad(qg_mlp *M, const float *x, const float *t, int B, double *loss, float *grad) {
+    if (!M || !x || !t || !loss || !grad) return fail(QG_EINVAL, "NULL argument");
+    if (B < 1) return fail(QG_EINVAL, "B < 1");
+    const size_t xb = (size_t)B * M->F * sizeof(float);
+    HIP_TRY(M->data.ensure(xb + B * sizeof(float) + 256, M->stream), "mlp input");
+    float *dx = static_cast<float *>(M->data.p);
+    float *dt = reinterpret_cast<float *>(static_cast<unsigned char *>(M->data.p) + ((xb + 255) & ~size_t(255)));
+    HIP_TRY(hipMemcpyAsync(dx, x, xb, hipMemcpyHostToDevice, M->stream), "mlp input");
+    HIP_TRY(hipMemcpyAsync(dt, t, B * sizeof(float), hipMemcpyHostToDevice, M->stream), "mlp target");
+    MlpAct a;
+    HIP_TRY(mlp_act(M, B, 1, &a), "mlp scratch");
+    HIP_TRY(hipMemsetAsync(a.loss, 0, sizeof(double), M->stream), "clear loss");
+    HIP_TRY(launch_mlp_grad(static_cast<float *>(M->theta.p), dx, dt, B, M->F, a.z1, a.z2, a.z3, a.y, a.dy, a.dz1,
+                            a.dz2, a.dz3, static_cast<float *>(M->grad.p), a.loss, 0, M->stream),
+            "mlp backward");
+    HIP_TRY(hipMemcpyAsync(grad, M->grad.p, M->P * sizeof(float), hipMemcpyDeviceToHost, M->stream), "mlp grad");
+    HIP_TRY(hipMemcpyAsync(loss, a.loss, sizeof(double), hipMemcpyDeviceToHost, M->stream), "mlp loss");
+    HIP_TRY(hipStreamSynchronize(M->stream), "mlp backward");
+    return QG_OK;
+}
+
+qg_status qg_mlp_adam_step(qg_mlp *M, const float *grad, float lr) {
+    if (!M || !grad) return fail(QG_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(M->grad.p, grad, M->P * sizeof(float), hipMemcpyHostToDevice, M->stream), "adam grad");
+    M->step++;
+    HIP_TRY(launch_mlp_adam(static_cast<float *>(M->theta.p), static_cast<float *>(M->grad.p),
+                            static_cast<float *>(M->m.p), static_cast<float *>(M->v.p), M->P, lr, M->step, M->stream),
+            "adam");
+    HIP_TRY(hipStreamSynchronize(M->stream), "adam");
+    return QG_OK;
+}
+
+qg_status qg_mlp_train(qg_mlp *M, const float *x, const float *t, int N, int epochs, int batch, float lr,
+                       uint64_t seed, double *loss_per_epoch) {
+    if (!M || !x || !t) return fail(QG_EINVAL, "NULL argument");
+    if (N < 1 || epochs < 0 || batch < 1) return fail(QG_EINVAL, "N, epochs or batch out of range");
+    if (batch > N) batch = N;
+    const size_t F = M->F;
+    const size_t xb = ((size_t)N * F * sizeof(float) + 255) & ~size_t(255);
+    const size_t tb = ((size_t)N * sizeof(float) + 255) & ~size_t(255);
+    const size_t ob = ((size_t)N * sizeof(int32_t) + 255) & ~size_t(255);
+    const size_t bb = ((size_t)batch * F * sizeof(float) + 255) & ~size_t(255);
+    HIP_TRY(M->data.ensure(xb + tb + ob + bb + batch * sizeof(float) + 256, M->stream), "training data");
+    unsigned char *base = static_cast<unsigned char *>(M->data.p);
+    float *dX = reinterpret_cast<float *>(base);
+    float *dT = reinterpret_cast<float *>(base + xb);
+    int32_t *dOrder = reinterpret_cast<int32_t *>(base + xb + tb);
+    float *dXb = reinterpret_cast<float *>(base + xb + tb + ob);
+    float *dTb = reinterpret_cast<float *>(base + xb + tb + ob + bb);
+    HIP_TRY(hipMemcpyAsync(dX, x, (size_t)N * F * sizeof(float), hipMemcpyHostToDevice, M->stream), "upload X");
+    HIP_TRY(hipMemcpyAsync(dT, t, (size_t)N * sizeof(float), hipMemcpyHostToDevice, M->stream), "upload T");
+    MlpAct a;
+    HIP_TRY(mlp_act(M, batch, epochs, &a), "mlp scratch");
+    if (epochs > 0) HIP_TRY(hipMemsetAsync(a.loss, 0, epochs * sizeof(double), M->stream), "clear losses");
+    std::vector<int32_t> order(N);
+    uint64_t state = seed;
+    auto next = [&]() {
+        uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    std::vector<int32_t> all_orders((size_t)N * std::max(epochs, 1));
+    for (int ep = 0; ep < epochs; ++ep) {
+        for (int i = 0; i < N; ++i) order[i] = i;
+        for (int i = N - 1; i > 0; --i) std::swap(order[i], order[next() % (uint64_t)(i + 1)]);
+        std::memcpy(all_orders.data() + (size_t)ep * N, order.data(), N * sizeof(int32_t));
+    }
+    const int nbat = N / batch;  // full batches only (the remainder reshuffles next epoch)
+    for (int ep = 0; ep < epochs; ++ep) {
+        HIP_TRY(hipMemcpyAsync(dOrder, all_orders.data() + (size_t)ep * N, N * sizeof(int32_t), hipMemcpyHostToDevice,
+                               M->stream),
+                "upload order");
+        for (int bi = 0; bi < nbat; ++bi) {
+            HIP_TRY(launch_mlp_gather(dX, dT, dOrder + (size_t)bi * batch, batch, M->F, dXb, dTb, M->stream), "gather");
+            HIP_TRY(launch_mlp_grad(static_cast<float *>(M->theta.p), dXb, dTb, batch, M->F, a.z1, a.z2, a.z3, a.y,
+                                    a.dy, a.dz1, a.dz2, a.dz3, static_cast<float *>(M->grad.p), a.loss, ep, M->stream),
+                    "mlp backward");
+            M->step++;
+            HIP_TRY(launch_mlp_adam(static_cast<float *>(M->theta.p), static_cast<float *>(M->grad.p),
+                                    static_cast<float *>(M->m.p), static_cast<float *>(M->v.p), M->P, lr, M->step,
+                                    M->stream),
+                    "adam");
+        }
+        // the order upload of the next epoch reads host memory: wait before reusing
+        HIP_TRY(hipStreamSynchronize(M->stream), "epoch");
+    }
+    if (loss_per_epoch && epochs > 0) {
+        std::vector<double> l(epochs);
+        HIP_TRY(hipMemcpy(l.data(), a.loss, epochs * sizeof(double), hipMemcpyDeviceToHost), "losses");
+        for (int ep = 0; ep < epochs; ++ep) loss_per_epoch[ep] = l[ep] / std::max(nbat, 1);
+    }
+    return QG_OK;
+}
+
+qg_status qg_mlp_free(qg_mlp *M) {
+    if (!M) return QG_OK;
+    if (g_cost_model == M) g_cost_model = nullptr;
+    (void)hipStreamSynchronize(M->stream);
+    delete M;
+    return QG_OK;
+}
+
+qg_status qg_pass_features(const qg_circuit *c, qg_dtype dtype, int config, float *features, int32_t *n_passes) {
+    std::string err;
+    if (validate_circuit(c, -1, &err) != QG_OK) return fail(QG_EINVAL, "%s", err.c_str());
+    if (dtype != QG_C64 && dtype != QG_C128) return fail(QG_EINVAL, "unknown dtype %d", (int)dtype);
+    if (config < 0 || config >= kPlanConfigs) return fail(QG_EINVAL, "config must be in [0, %d)", kPlanConfigs);
+    if (!features) return fail(QG_EINVAL, "features is NULL");
+    if (c->n_gates < 1) return fail(QG_EINVAL, "empty circuit");
+    std::vector<Gate> g = load_gates(c);
+    PlanConfig cfg = candidate_config(c->n_qubits, dtype == QG_C64, config);
+    if (n_passes) *n_passes = (int32_t)fuse(g, cfg).size();
+    pass_features(g, 0, (int)g.size(), cfg, features);
+    return QG_OK;
+}
+
+qg_status qg_set_cost_model(qg_mlp *M) {
+    if (M && M->F != kPlanFeatures)
+        return fail(QG_EINVAL, "cost model takes %d inputs, pass features are %d", M->F, kPlanFeatures);
+    g_cost_model = M;
+    return QG_OK;
 }
 
 }  // extern "C"

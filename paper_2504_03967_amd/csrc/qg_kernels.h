@@ -69,4 +69,19 @@ struct BatchLaunch {
 };
 hipError_t launch_batch(bool c64, int rb, const BatchLaunch &L, hipStream_t st);
 
+// Cost-model MLP (FP32, hidden width kMlpHidden).  z1..z3, dz1..dz3: [B][H] scratch.
+constexpr int kMlpHidden = 64;
+int mlp_param_count(int n_in);
+hipError_t launch_mlp_forward(const float *theta, const float *X, int B, int F, float *z1, float *z2, float *z3,
+                              float *y, hipStream_t st);
+// Forward, loss (mean squared error; added to loss_acc[loss_slot] when not NULL),
+// backward: grad[P] for the batch.
+hipError_t launch_mlp_grad(const float *theta, const float *X, const float *T, int B, int F, float *z1, float *z2,
+                           float *z3, float *y, float *dy, float *dz1, float *dz2, float *dz3, float *grad,
+                           double *loss_acc, int loss_slot, hipStream_t st);
+hipError_t launch_mlp_adam(float *theta, const float *g, float *m, float *v, int n, float lr, int step,
+                           hipStream_t st);
+hipError_t launch_mlp_gather(const float *X, const float *T, const int32_t *idx, int B, int F, float *Xb, float *Tb,
+                             hipStream_t st);
+
 }  // namespace qg

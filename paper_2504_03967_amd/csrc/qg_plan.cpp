@@ -472,4 +472,80 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
     return prog;
 }
 
+void append_program(Program *dst, const Program &src) {
+    const int ph0 = (int)dst->phases.size(), op0 = (int)dst->ops.size(), pass0 = (int)dst->passes.size();
+    for (PassDesc pd : src.passes) {
+        pd.phase_begin += ph0;
+        dst->passes.push_back(pd);
+    }
+    for (PhaseDesc ph : src.phases) {
+        ph.op_begin += op0;
+        ph.op_end += op0;
+        dst->phases.push_back(ph);
+    }
+    dst->ops.insert(dst->ops.end(), src.ops.begin(), src.ops.end());
+    (void)pass0;
+}
+
+PlanConfig candidate_config(int n, bool c64, int k) {
+    PlanConfig c = default_config(n, c64, QG_FUSE_GREEDY);
+    // max_high = 4 + k; low_bits fills the rest of the tile
+    c.max_high = 4 + k;
+    c.low_bits = c.tile_bits - c.max_high;
+    clamp_config(&c);
+    return c;
+}
+
+int first_block_end(const std::vector<Gate> &g, int begin, const PlanConfig &cfg) {
+    const int G = (int)g.size();
+    const int n = cfg.n;
+    const int b = std::min(n, cfg.tile_bits);
+    const int low = n <= b ? n : std::min(cfg.low_bits, b);
+    const uint64_t low_mask = low >= 64 ? ~0ull : ((1ull << low) - 1);
+    const int max_high = n <= b ? 64 : std::min(cfg.max_high, b - low);
+    uint64_t high = 0;
+    int i = begin;
+    for (; i < G; ++i) {
+        const uint64_t req = required_qubits(g[i]) & ~low_mask;
+        if (i > begin && (popcount64(high | req) > max_high || i - begin >= cfg.max_gates_per_pass)) break;
+        high |= req;
+    }
+    return i;
+}
+
+// Scaled features (see the cost-model kernels): qubits, precision, log2 of the
+// active fraction and of the bytes moved, gate / op / phase counts, required
+// qubits (all, and outside the low block), tile shape, fusion knobs, and the
+// count of each gate code.
+void pass_features(const std::vector<Gate> &g, int begin, int end, const PlanConfig &cfg, float *f) {
+    std::vector<Gate> sub(g.begin() + begin, g.begin() + end);
+    std::vector<PassRange> one{{0, (int)sub.size()}};
+    Program p = build_program(sub, one, cfg);
+    const PassDesc &pd = p.passes[0];
+    uint64_t req = 0;
+    int counts[10] = {0};
+    for (const Gate &x : sub) {
+        req |= required_qubits(x);
+        counts[x.op]++;
+    }
+    const int fixed = popcount64(pd.fixed_mask);
+    const int sbits = cfg.c64 ? 3 : 4;
+    const uint64_t low_mask = cfg.low_bits >= 64 ? ~0ull : ((1ull << cfg.low_bits) - 1);
+    f[0] = cfg.n / 32.f;
+    f[1] = cfg.c64 ? 0.f : 1.f;
+    f[2] = -fixed / 4.f;
+    f[3] = (cfg.n + sbits + 1 - fixed - 30) / 4.f;
+    f[4] = sub.size() / 32.f;
+    f[5] = p.ops.size() / 32.f;
+    f[6] = pd.n_phase / 8.f;
+    f[7] = (pd.n_phase - 1) / 8.f;
+    f[8] = popcount64(req) / 8.f;
+    f[9] = popcount64(req & ~low_mask) / 8.f;
+    f[10] = pd.b / 16.f;
+    f[11] = pd.rb / 5.f;
+    f[12] = cfg.low_bits / 16.f;
+    f[13] = cfg.max_high / 8.f;
+    for (int k = 0; k < 10; ++k) f[14 + k] = counts[k] / 16.f;
+}
+
 }  // namespace qg

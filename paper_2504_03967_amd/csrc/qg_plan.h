@@ -82,6 +82,20 @@ std::vector<PassRange> fuse(const std::vector<Gate> &g, const PlanConfig &cfg);
 Program build_program(const std::vector<Gate> &g, const std::vector<PassRange> &passes,
                       const PlanConfig &cfg);
 
+// Appends a program's passes, phases and ops (offsetting their indices); pass_of_gate is not merged.
+void append_program(Program *dst, const Program &src);
+
+// ---- learned fusion: features of one candidate pass
+constexpr int kPlanFeatures = 24;
+// Candidate (low_bits, max_high) fusion configurations per dtype; index 1 is the
+// greedy default (width 5).
+constexpr int kPlanConfigs = 4;
+PlanConfig candidate_config(int n, bool c64, int k);
+// End of the pass the greedy rule would form starting at gate `begin`.
+int first_block_end(const std::vector<Gate> &g, int begin, const PlanConfig &cfg);
+// Features of gates [begin, end) executed as one pass under cfg (scaled, see the .cpp).
+void pass_features(const std::vector<Gate> &g, int begin, int end, const PlanConfig &cfg, float *f);
+
 // 2x2 matrix of a single-qubit gate (textbook forms, header of qg.h).
 void gate_matrix(int op, const double *p, cd m[2][2]);
 

@@ -26,7 +26,11 @@ EXPORTS = (
     "qg_apply_circuit", "qg_probs", "qg_sample", "qg_expval", "qg_adjoint_grad", "qg_batch_expval",
     "qg_plan_passes", "qg_last_error", "qg_version", "qg_set_tuning", "qg_get_tuning",
     "qg_batch_create", "qg_batch_set_params", "qg_batch_launch", "qg_batch_free",
+    "qg_mlp_create", "qg_mlp_n_params", "qg_mlp_set_params", "qg_mlp_get_params", "qg_mlp_forward",
+    "qg_mlp_grad", "qg_mlp_adam_step", "qg_mlp_train", "qg_mlp_free", "qg_pass_features", "qg_set_cost_model",
 )
+PASS_FEATURES = 24
+PASS_CONFIGS = 4
 
 
 class QGError(RuntimeError):
@@ -64,6 +68,17 @@ def _load() -> ctypes.CDLL:
         "qg_batch_set_params": [P, P],
         "qg_batch_launch": [P],
         "qg_batch_free": [P],
+        "qg_mlp_create": [ctypes.c_int, ctypes.c_int, U64, P, P],
+        "qg_mlp_n_params": [P, P],
+        "qg_mlp_set_params": [P, P],
+        "qg_mlp_get_params": [P, P],
+        "qg_mlp_forward": [P, P, ctypes.c_int, P],
+        "qg_mlp_grad": [P, P, P, ctypes.c_int, P, P],
+        "qg_mlp_adam_step": [P, P, ctypes.c_float],
+        "qg_mlp_train": [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float, U64, P],
+        "qg_mlp_free": [P],
+        "qg_pass_features": [P, ctypes.c_int, ctypes.c_int, P, P],
+        "qg_set_cost_model": [P],
         "qg_set_tuning": [ctypes.c_char_p, I64],
         "qg_get_tuning": [ctypes.c_char_p, P],
     }
@@ -281,6 +296,84 @@ def batch_expval(circs, dtype="c128", obs=None, stream=None) -> torch.Tensor:
                                None if coeffs is None else coeffs.ctypes.data,
                                _stream_handle(stream), ctypes.c_void_p(out.data_ptr())))
     return out[:len(circs)]
+
+
+class MLP:
+    """The library's cost-model MLP (FP32, three ReLU hidden layers of width 64)."""
+
+    def __init__(self, n_in: int = PASS_FEATURES, seed: int = 0, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib.qg_mlp_create(int(n_in), 64, int(seed) & ((1 << 64) - 1), _stream_handle(stream),
+                                 ctypes.byref(h)))
+        self.handle = h
+        self.n_in = int(n_in)
+        n = ctypes.c_int64()
+        _check(lib.qg_mlp_n_params(h, ctypes.byref(n)))
+        self.n_params = int(n.value)
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, np.float32)
+        _check(lib.qg_mlp_get_params(self.handle, out.ctypes.data))
+        return out
+
+    def set_params(self, theta) -> None:
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        assert th.size == self.n_params
+        _check(lib.qg_mlp_set_params(self.handle, th.ctypes.data))
+
+    def forward(self, X) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, self.n_in)
+        y = np.empty(X.shape[0], np.float32)
+        _check(lib.qg_mlp_forward(self.handle, X.ctypes.data, X.shape[0], y.ctypes.data))
+        return y
+
+    def grad(self, X, t):
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, self.n_in)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        g = np.empty(self.n_params, np.float32)
+        loss = ctypes.c_double()
+        _check(lib.qg_mlp_grad(self.handle, X.ctypes.data, t.ctypes.data, X.shape[0], ctypes.byref(loss),
+                               g.ctypes.data))
+        return float(loss.value), g
+
+    def adam_step(self, g, lr: float) -> None:
+        g = np.ascontiguousarray(g, dtype=np.float32)
+        _check(lib.qg_mlp_adam_step(self.handle, g.ctypes.data, float(lr)))
+
+    def train(self, X, t, epochs: int, batch: int, lr: float, seed: int = 0) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, self.n_in)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        losses = np.zeros(max(epochs, 1), np.float64)
+        _check(lib.qg_mlp_train(self.handle, X.ctypes.data, t.ctypes.data, X.shape[0], int(epochs), int(batch),
+                                float(lr), int(seed), losses.ctypes.data))
+        return losses[:epochs]
+
+    def install(self) -> None:
+        _check(lib.qg_set_cost_model(self.handle))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib.qg_mlp_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def clear_cost_model() -> None:
+    _check(lib.qg_set_cost_model(None))
+
+
+def pass_features(circ, dtype="c128", config: int = 1):
+    """(features of the whole circuit as one pass under candidate config, greedy pass count)."""
+    ca = CircuitArgs(circ)
+    f = np.empty(PASS_FEATURES, np.float32)
+    npass = ctypes.c_int32()
+    _check(lib.qg_pass_features(ca.ptr, _dtype_code(dtype), int(config), f.ctypes.data, ctypes.byref(npass)))
+    return f, int(npass.value)
 
 
 def plan_passes(circ, dtype="c128", fusion: int = FUSE_GREEDY):
