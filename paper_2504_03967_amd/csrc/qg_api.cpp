@@ -170,7 +170,7 @@ size_t amp_bytes(qg_dtype dt) { return dt == QG_C64 ? 8 : 16; }
 int max_qubits(qg_dtype dt) { return dt == QG_C64 ? 34 : 33; }
 
 bool fits_inline(const Program &prog, const PassDesc &pd) {
-    if (pd.n_phase > kInlinePhases) return false;
+    if ((pd.flags & PASS_DENSE) || pd.n_phase > kInlinePhases) return false;
     const PhaseDesc &first = prog.phases[pd.phase_begin];
     const PhaseDesc &last = prog.phases[pd.phase_begin + pd.n_phase - 1];
     return last.op_end - first.op_begin <= kInlineOps;
@@ -196,13 +196,20 @@ qg_status run_program(Ctx &cx, bool c64, const Program &prog, void *psi, void *l
     if (prog.passes.empty()) return QG_OK;
     bool need_upload = false;
     for (const PassDesc &pd : prog.passes) need_upload |= !fits_inline(prog, pd);
-    size_t pass_off = 0, phase_off = 0, op_off = 0;
+    size_t pass_off = 0, phase_off = 0, op_off = 0, ut_off = 0;
     unsigned char *dev = nullptr;
+    const size_t ut_size = c64 ? sizeof(float) : sizeof(double);
     if (need_upload) {
         Pack pk;
         pass_off = pk.add(prog.passes);
         phase_off = pk.add(prog.phases);
         op_off = pk.add(prog.ops);
+        if (c64) {
+            std::vector<float> f(prog.dense_ut.begin(), prog.dense_ut.end());
+            ut_off = pk.add(f);
+        } else {
+            ut_off = pk.add(prog.dense_ut);
+        }
         HIP_TRY(cx.push(pk, &dev), "upload program");
     }
     const int ns = lam ? 2 : 1;
@@ -214,6 +221,13 @@ qg_status run_program(Ctx &cx, bool c64, const Program &prog, void *psi, void *l
     InlineProg inl;
     for (size_t p = 0; p < prog.passes.size(); ++p) {
         const PassDesc &pd = prog.passes[p];
+        if (pd.flags & PASS_DENSE) {
+            const DenseDesc &D = prog.dense[pd.phase_begin];
+            const unsigned char *ut = dev + ut_off + (size_t)D.u_index * ut_size;
+            HIP_TRY(launch_dense(c64, D, ut, ut + ((size_t)1 << (2 * D.k)) * ut_size, psi, cx.stream),
+                    "dense block launch");
+            continue;
+        }
         const int64_t waves = pd.tb >= 6 ? (int64_t(1) << pd.tb) / 64 : 1;
         const int64_t gstride = (int64_t)pd.n_tiles * waves;
         const bool small = fits_inline(prog, pd);
@@ -721,7 +735,7 @@ qg_status qg_apply_circuit(qg_state *s, const qg_circuit *c, int fusion_mode) {
         prog = build_learned(g, e, s->n, s->c64());
     } else {
         PlanConfig cfg = plan_config(s->n, s->c64(), fusion_mode);
-        prog = build_program(g, fuse(g, cfg), cfg);
+        prog = build_plan(g, cfg);
     }
     return run_program(s->cx, s->c64(), prog, s->buf, nullptr, nullptr);
 }

@@ -65,7 +65,20 @@ struct PassDesc {
 };
 
 enum PassFlags : int32_t {
-    PASS_NT = 1,  // non-temporal loads and stores of the state (streaming, no reuse)
+    PASS_NT = 1,     // non-temporal loads and stores of the state (streaming, no reuse)
+    PASS_DENSE = 2,  // the pass is a dense block: phase_begin indexes the program's DenseDesc list
+};
+
+// A dense k-qubit block (k in 4..6): tiles are the block qubits blk_q plus the l
+// lowest other qubits low_q; the rest are free runs enumerated by the block index.
+struct DenseDesc {
+    int32_t k, l, n_runs, pad;
+    int8_t blk_q[8];
+    int8_t low_q[16];
+    int32_t run_start[kMaxRuns];
+    int32_t run_len[kMaxRuns];
+    uint64_t n_tiles;
+    int64_t u_index;  // first element of this block's transposed matrix in the program's matrix list
 };
 
 // One circuit of a batched launch: its passes are passes[pass_begin, +n_pass);

@@ -49,6 +49,10 @@ hipError_t launch_grad_rows(const double *gpart, int64_t gstride, int64_t count,
 hipError_t launch_grad_slots(const double *rows, const int32_t *row_slot, int n_rows, double *grad,
                              int n_params, hipStream_t st);
 
+// Dense block on the matrix cores; ut_re/ut_im: transposed 2^k x 2^k matrix (R precision).
+hipError_t launch_dense(bool c64, const DenseDesc &D, const void *ut_re, const void *ut_im, void *psi,
+                        hipStream_t st);
+
 // Batched persistent launch (all pointers are device pointers).
 struct BatchLaunch {
     const BatchCirc *circs;

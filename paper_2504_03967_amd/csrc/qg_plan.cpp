@@ -147,6 +147,7 @@ const Knob kKnobs[] = {
     {"max_high_c64", [](Tuning &t) { return &t.max_high[1]; }, 1, 14},
     {"nt", [](Tuning &t) { return &t.nt; }, 0, 1},
     {"swz_bits", [](Tuning &t) { return &t.swz_bits; }, 0, 16},
+    {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 1, 1 << 30},
 };
 }  // namespace
 
@@ -184,6 +185,7 @@ PlanConfig default_config(int n, bool c64, int fusion) {
     c.max_high = std::max(1, std::min(t.max_high[d], c.tile_bits - c.low_bits));
     c.flags = t.nt ? PASS_NT : 0;
     c.swz_bits = t.swz_bits;
+    c.dense_min_gates = t.dense_min_gates;
     return c;
 }
 
@@ -472,12 +474,151 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
     return prog;
 }
 
+uint64_t touched_qubits(const Gate &g) {
+    uint64_t m = 1ull << g.q1;
+    if (g.op >= QG_CX) m |= 1ull << g.q0;
+    return m;
+}
+
+uint64_t dense_block_qubits(const std::vector<Gate> &g, int begin, int end, int n) {
+    uint64_t q = 0;
+    for (int i = begin; i < end; ++i) q |= touched_qubits(g[i]);
+    if (popcount64(q) > 6 || n < 8 || n - std::max(4, popcount64(q)) < 4) return 0;
+    // at least 4 block qubits (16-row matrix tiles): add the highest untouched qubits
+    for (int b = n - 1; b >= 0 && popcount64(q) < 4; --b) q |= 1ull << b;
+    return q;
+}
+
+namespace {
+
+// Column-by-column product U <- G U on the k block qubits (local bit j = j-th block qubit).
+void dense_apply(std::vector<cd> &U, int k, const Gate &g, const int *local_of) {
+    const int dim = 1 << k;
+    const int t = local_of[g.q1];
+    const int c = g.op >= QG_CX ? local_of[g.q0] : -1;
+    cd m[2][2];
+    if (g.op <= QG_U3) gate_matrix(g.op, g.p, m);
+    for (int col = 0; col < dim; ++col) {
+        cd *v = U.data() + (size_t)col;  // element r of column col is U[r * dim + col]
+        auto at = [&](int r) -> cd & { return v[(size_t)r * dim]; };
+        for (int r = 0; r < dim; ++r) {
+            const int bt = (r >> t) & 1;
+            switch (g.op) {
+            case QG_CX:
+                if (((r >> c) & 1) && !bt) std::swap(at(r), at(r | (1 << t)));
+                break;
+            case QG_CZ:
+                if (((r >> c) & 1) && bt) at(r) = -at(r);
+                break;
+            case QG_CP:
+                if (((r >> c) & 1) && bt) at(r) *= std::polar(1.0, g.p[0]);
+                break;
+            case QG_SWAP:
+                if (((r >> c) & 1) && !bt) std::swap(at(r), at((r ^ (1 << c)) | (1 << t)));
+                break;
+            default:
+                if (!bt) {
+                    const cd a0 = at(r), a1 = at(r | (1 << t));
+                    at(r) = m[0][0] * a0 + m[0][1] * a1;
+                    at(r | (1 << t)) = m[1][0] * a0 + m[1][1] * a1;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+void append_dense(Program *prog, const std::vector<Gate> &g, int begin, int end, uint64_t blk, const PlanConfig &cfg) {
+    const int n = cfg.n;
+    DenseDesc D{};
+    int local_of[64];
+    for (int q = 0; q < 64; ++q) local_of[q] = -1;
+    int k = 0;
+    for (int q = 0; q < n; ++q)
+        if (blk >> q & 1) {
+            local_of[q] = k;
+            D.blk_q[k++] = (int8_t)q;
+        }
+    D.k = k;
+    const int tile = std::min(n, cfg.tile_bits);
+    const int l = std::min(tile - k, n - k);
+    int li = 0;
+    uint64_t used = blk;
+    for (int q = 0; q < n && li < l; ++q)
+        if (!(blk >> q & 1)) {
+            D.low_q[li++] = (int8_t)q;
+            used |= 1ull << q;
+        }
+    D.l = li;
+    int free_bits = 0;
+    for (int q = 0; q < n; ++q) {
+        if (used >> q & 1) continue;
+        if (D.n_runs > 0 && D.run_start[D.n_runs - 1] + D.run_len[D.n_runs - 1] == q) {
+            D.run_len[D.n_runs - 1]++;
+        } else {
+            D.run_start[D.n_runs] = q;
+            D.run_len[D.n_runs] = 1;
+            D.n_runs++;
+        }
+        free_bits++;
+    }
+    D.n_tiles = 1ull << free_bits;
+    const int dim = 1 << k;
+    std::vector<cd> U((size_t)dim * dim, 0.0);
+    for (int r = 0; r < dim; ++r) U[(size_t)r * dim + r] = 1.0;
+    for (int i = begin; i < end; ++i) dense_apply(U, k, g[i], local_of);
+    D.u_index = (int64_t)prog->dense_ut.size();
+    // transposed: UT[c][r] = U[r][c]; re block then im block
+    for (int part = 0; part < 2; ++part)
+        for (int c = 0; c < dim; ++c)
+            for (int r = 0; r < dim; ++r) {
+                const cd v = U[(size_t)r * dim + c];
+                prog->dense_ut.push_back(part ? v.imag() : v.real());
+            }
+    PassDesc pd{};
+    pd.flags = PASS_DENSE;
+    pd.phase_begin = (int)prog->dense.size();
+    pd.n_phase = 0;
+    pd.n_tiles = D.n_tiles;
+    pd.b = k + li;
+    prog->dense.push_back(D);
+    prog->passes.push_back(pd);
+}
+
+Program build_plan(const std::vector<Gate> &g, const PlanConfig &cfg) {
+    std::vector<PassRange> ranges = fuse(g, cfg);
+    if (cfg.dense_min_gates >= (1 << 30) || cfg.reverse || cfg.n < 8) return build_program(g, ranges, cfg);
+    Program prog;
+    prog.pass_of_gate.assign(g.size(), -1);
+    for (size_t p = 0; p < ranges.size(); ++p) {
+        const PassRange &r = ranges[p];
+        const uint64_t blk = r.g_end - r.g_begin >= cfg.dense_min_gates
+                                 ? dense_block_qubits(g, r.g_begin, r.g_end, cfg.n) : 0;
+        if (blk) {
+            append_dense(&prog, g, r.g_begin, r.g_end, blk, cfg);
+        } else {
+            std::vector<PassRange> one{r};
+            append_program(&prog, build_program(g, one, cfg));
+        }
+        for (int i = r.g_begin; i < r.g_end; ++i) prog.pass_of_gate[i] = (int)p;
+    }
+    return prog;
+}
+
 void append_program(Program *dst, const Program &src) {
     const int ph0 = (int)dst->phases.size(), op0 = (int)dst->ops.size(), pass0 = (int)dst->passes.size();
+    const int d0 = (int)dst->dense.size();
+    const int64_t u0 = (int64_t)dst->dense_ut.size();
     for (PassDesc pd : src.passes) {
-        pd.phase_begin += ph0;
+        pd.phase_begin += (pd.flags & PASS_DENSE) ? d0 : ph0;
         dst->passes.push_back(pd);
     }
+    for (DenseDesc d : src.dense) {
+        d.u_index += u0;
+        dst->dense.push_back(d);
+    }
+    dst->dense_ut.insert(dst->dense_ut.end(), src.dense_ut.begin(), src.dense_ut.end());
     for (PhaseDesc ph : src.phases) {
         ph.op_begin += op0;
         ph.op_end += op0;

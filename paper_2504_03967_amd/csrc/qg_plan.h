@@ -30,6 +30,7 @@ struct PlanConfig {
     int flags = 0;        // PASS_* bits for every pass
     int swz_bits = 0;     // tile-order swizzle of the block index
     int max_gates_per_pass = 4096;
+    int dense_min_gates = 1 << 30;  // a pass on <= 6 qubits with this many gates runs as a dense block
 };
 
 // Process-wide tuning of the planner (defaults measured on MI355X; set by
@@ -41,6 +42,7 @@ struct Tuning {
     int max_high[2] = {5, 5};
     int nt = 1;
     int swz_bits = 0;
+    int dense_min_gates = 1 << 30;
 };
 Tuning &tuning();
 // Returns 0 on success, -1 for an unknown key or out-of-range value.
@@ -63,6 +65,8 @@ struct Program {
     std::vector<int> pass_of_gate;   // index into execution order
     std::vector<int> grad_row_slot;  // adjoint: parameter slot of each gradient row
     int64_t max_grad_part = 0;       // adjoint: largest per-pass partial-sum block (doubles)
+    std::vector<DenseDesc> dense;    // dense steps (passes flagged PASS_DENSE)
+    std::vector<double> dense_ut;    // their transposed matrices: re block then im block, 4^k each
 };
 
 // Validates a circuit (qubits in range, q0 != q1, known code, finite params,
@@ -81,6 +85,16 @@ std::vector<PassRange> fuse(const std::vector<Gate> &g, const PlanConfig &cfg);
 // Device program for the given pass partition.
 Program build_program(const std::vector<Gate> &g, const std::vector<PassRange> &passes,
                       const PlanConfig &cfg);
+
+// All qubits a gate touches (targets, controls, diagonal qubits).
+uint64_t touched_qubits(const Gate &g);
+// Dense step of gates [begin, end) on block qubits `blk` (4..6 qubits, covering
+// every touched qubit); appended to prog as a PASS_DENSE pass.
+void append_dense(Program *prog, const std::vector<Gate> &g, int begin, int end, uint64_t blk, const PlanConfig &cfg);
+// Block qubits for a dense step of gates [begin, end), or 0 if they touch more than 6 qubits.
+uint64_t dense_block_qubits(const std::vector<Gate> &g, int begin, int end, int n);
+// Greedy plan with the dense rule applied (cfg.dense_min_gates).
+Program build_plan(const std::vector<Gate> &g, const PlanConfig &cfg);
 
 // Appends a program's passes, phases and ops (offsetting their indices); pass_of_gate is not merged.
 void append_program(Program *dst, const Program &src);

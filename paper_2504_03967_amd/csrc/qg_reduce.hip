@@ -19,6 +19,9 @@ __device__ __forceinline__ double prob(C v) {
     return x * x + y * y;
 }
 
+__device__ __forceinline__ int popc(uint32_t x) { return __popc(x); }
+__device__ __forceinline__ int popc(uint64_t x) { return __popcll(x); }
+
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
@@ -71,36 +74,62 @@ inline int expval_blocks(uint64_t dim) {
     return (int)b;
 }
 
-template <typename R, int TM>
+// Each block reduces a contiguous chunk.  Per term the thread accumulates the
+// probability mass of odd parity; <Z_m> = total - 2 odd_m.  Indices below 2^32
+// use 32-bit parity arithmetic (IDX = uint32_t).
+template <typename R, int TM, typename IDX>
 __global__ void __launch_bounds__(kThreads)
 k_expval_part(const typename V2<R>::T *__restrict__ psi, uint64_t dim, const uint64_t *__restrict__ masks,
               int n_terms, int term0, double *__restrict__ part, int nblocks) {
-    __shared__ double red[TM][kThreads / 64];
-    uint64_t mk[TM];
+    using C = typename V2<R>::T;
+    constexpr int U = 4;
+    __shared__ double red[TM + 1][kThreads / 64];
+    IDX mk[TM];
 #pragma unroll
-    for (int t = 0; t < TM; ++t) mk[t] = term0 + t < n_terms ? masks[term0 + t] : 0;
-    double acc[TM];
+    for (int t = 0; t < TM; ++t) mk[t] = term0 + t < n_terms ? (IDX)masks[term0 + t] : (IDX)0;
+    double odd[TM], total = 0.0;
 #pragma unroll
-    for (int t = 0; t < TM; ++t) acc[t] = 0.0;
+    for (int t = 0; t < TM; ++t) odd[t] = 0.0;
     const uint64_t chunk = (dim + nblocks - 1) / nblocks;
     const uint64_t lo = blockIdx.x * chunk;
     const uint64_t hi = lo + chunk < dim ? lo + chunk : dim;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
-        const double p = prob(psi[i]);
+    uint64_t i = lo + threadIdx.x;
+    for (; i + (U - 1) * kThreads < hi; i += U * kThreads) {
+        C v[U];
 #pragma unroll
-        for (int t = 0; t < TM; ++t) acc[t] += (__popcll(i & mk[t]) & 1) ? -p : p;
+        for (int u = 0; u < U; ++u) v[u] = psi[i + u * kThreads];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double p = prob(v[u]);
+            const IDX ii = (IDX)(i + u * kThreads);
+            total += p;
+#pragma unroll
+            for (int t = 0; t < TM; ++t) odd[t] += (popc(ii & mk[t]) & 1) ? p : 0.0;
+        }
+    }
+    for (; i < hi; i += kThreads) {
+        const double p = prob(psi[i]);
+        const IDX ii = (IDX)i;
+        total += p;
+#pragma unroll
+        for (int t = 0; t < TM; ++t) odd[t] += (popc(ii & mk[t]) & 1) ? p : 0.0;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double tw = wave_sum(total);
+    if (lane == 0) red[TM][wave] = tw;
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
-        const double v = wave_sum(acc[t]);
+        const double v = wave_sum(odd[t]);
         if (lane == 0) red[t][wave] = v;
     }
     __syncthreads();
     if (threadIdx.x < TM && term0 + (int)threadIdx.x < n_terms) {
-        double s = 0.0;
-        for (int w = 0; w < kThreads / 64; ++w) s += red[threadIdx.x][w];
-        part[(int64_t)(term0 + threadIdx.x) * nblocks + blockIdx.x] = s;
+        double so = 0.0, st = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) {
+            so += red[threadIdx.x][w];
+            st += red[TM][w];
+        }
+        part[(int64_t)(term0 + threadIdx.x) * nblocks + blockIdx.x] = st - 2.0 * so;
     }
 }
 
@@ -147,17 +176,33 @@ Levels make_levels(uint64_t dim) {
     return L;
 }
 
-// One wave per node: node j of the output = sum of inputs [64 j, 64 j + 64).
+// One wave per kLeafNodes consecutive nodes: node j of the output = sum of
+// probabilities [64 j, 64 j + 64); all loads of a lane are issued together.
+constexpr int kLeafNodes = 8;
+
 template <typename R>
 __global__ void k_tree_leaf(const typename V2<R>::T *__restrict__ psi, uint64_t dim, double *__restrict__ out,
                             uint64_t nout) {
-    const uint64_t node = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+    using C = typename V2<R>::T;
+    const uint64_t wave_id = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (node >= nout) return;  // whole waves exit together (blockDim is a multiple of 64)
-    const uint64_t i = node * kFan + lane;
-    double v = i < dim ? prob(psi[i]) : 0.0;
-    v = wave_sum(v);
-    if (lane == 0) out[node] = v;
+    const uint64_t node0 = wave_id * kLeafNodes;
+    if (node0 >= nout) return;  // whole waves exit together (blockDim is a multiple of 64)
+    C v[kLeafNodes];
+#pragma unroll
+    for (int k = 0; k < kLeafNodes; ++k) {
+        const uint64_t i = (node0 + k) * kFan + lane;
+        if (i < dim) v[k] = psi[i];
+        else {
+            v[k].x = (R)0;
+            v[k].y = (R)0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kLeafNodes; ++k) {
+        const double s = wave_sum(prob(v[k]));
+        if (lane == 0 && node0 + k < nout) out[node0 + k] = s;
+    }
 }
 
 __global__ void k_tree_up(const double *__restrict__ in, uint64_t nin, double *__restrict__ out, uint64_t nout) {
@@ -301,21 +346,31 @@ hipError_t launch_expval(bool c64, const void *psi, uint64_t dim, const uint64_t
                          int n_terms, double *part, double *out_terms, double *out_sum, hipStream_t st) {
     if (n_terms <= 0) return hipSuccess;
     const int nb = expval_blocks(dim);
+    const bool w64 = dim > (1ull << 32);
+#define QG_EXPVAL_LAUNCH(TM)                                                                                      \
+    do {                                                                                                          \
+        if (c64 && w64)                                                                                           \
+            hipLaunchKernelGGL((k_expval_part<float, TM, uint64_t>), dim3(nb), dim3(kThreads), 0, st,              \
+                               (const float2 *)psi, dim, masks, n_terms, t0, part, nb);                           \
+        else if (c64)                                                                                             \
+            hipLaunchKernelGGL((k_expval_part<float, TM, uint32_t>), dim3(nb), dim3(kThreads), 0, st,              \
+                               (const float2 *)psi, dim, masks, n_terms, t0, part, nb);                           \
+        else if (w64)                                                                                             \
+            hipLaunchKernelGGL((k_expval_part<double, TM, uint64_t>), dim3(nb), dim3(kThreads), 0, st,             \
+                               (const double2 *)psi, dim, masks, n_terms, t0, part, nb);                          \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_expval_part<double, TM, uint32_t>), dim3(nb), dim3(kThreads), 0, st,             \
+                               (const double2 *)psi, dim, masks, n_terms, t0, part, nb);                          \
+    } while (0)
     for (int t0 = 0; t0 < n_terms; t0 += kTermsPerPass) {
         const int left = n_terms - t0;
-        if (left <= 1) {
-            if (c64) hipLaunchKernelGGL((k_expval_part<float, 1>), dim3(nb), dim3(kThreads), 0, st, (const float2 *)psi, dim, masks, n_terms, t0, part, nb);
-            else hipLaunchKernelGGL((k_expval_part<double, 1>), dim3(nb), dim3(kThreads), 0, st, (const double2 *)psi, dim, masks, n_terms, t0, part, nb);
-        } else if (left <= 4) {
-            if (c64) hipLaunchKernelGGL((k_expval_part<float, 4>), dim3(nb), dim3(kThreads), 0, st, (const float2 *)psi, dim, masks, n_terms, t0, part, nb);
-            else hipLaunchKernelGGL((k_expval_part<double, 4>), dim3(nb), dim3(kThreads), 0, st, (const double2 *)psi, dim, masks, n_terms, t0, part, nb);
-        } else {
-            if (c64) hipLaunchKernelGGL((k_expval_part<float, kTermsPerPass>), dim3(nb), dim3(kThreads), 0, st, (const float2 *)psi, dim, masks, n_terms, t0, part, nb);
-            else hipLaunchKernelGGL((k_expval_part<double, kTermsPerPass>), dim3(nb), dim3(kThreads), 0, st, (const double2 *)psi, dim, masks, n_terms, t0, part, nb);
-        }
+        if (left <= 1) QG_EXPVAL_LAUNCH(1);
+        else if (left <= 4) QG_EXPVAL_LAUNCH(4);
+        else QG_EXPVAL_LAUNCH(kTermsPerPass);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+#undef QG_EXPVAL_LAUNCH
     double *terms = part + (int64_t)n_terms * nb;
     hipLaunchKernelGGL(k_expval_final, dim3(1), dim3(kThreads), 0, st, part, nb, n_terms, coeff, terms, out_terms,
                        out_sum);
@@ -338,8 +393,9 @@ hipError_t launch_sample(bool c64, const void *psi, uint64_t dim, int64_t shots,
         const uint64_t nout = L.size[l];
         const uint32_t g = (uint32_t)((nout * 64 + kThreads - 1) / kThreads);
         if (l == 1) {
-            if (c64) hipLaunchKernelGGL(k_tree_leaf<float>, dim3(g), dim3(kThreads), 0, st, (const float2 *)psi, dim, tree + L.off[1], nout);
-            else hipLaunchKernelGGL(k_tree_leaf<double>, dim3(g), dim3(kThreads), 0, st, (const double2 *)psi, dim, tree + L.off[1], nout);
+            const uint32_t gl = (uint32_t)(((nout + kLeafNodes - 1) / kLeafNodes * 64 + kThreads - 1) / kThreads);
+            if (c64) hipLaunchKernelGGL(k_tree_leaf<float>, dim3(gl), dim3(kThreads), 0, st, (const float2 *)psi, dim, tree + L.off[1], nout);
+            else hipLaunchKernelGGL(k_tree_leaf<double>, dim3(gl), dim3(kThreads), 0, st, (const double2 *)psi, dim, tree + L.off[1], nout);
         } else {
             hipLaunchKernelGGL(k_tree_up, dim3(g), dim3(kThreads), 0, st, tree + L.off[l - 1], L.size[l - 1],
                                tree + L.off[l], nout);

@@ -1,0 +1,64 @@
+"""Dense k-qubit blocks on the matrix cores against the oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2504_03967_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+@pytest.fixture
+def qg_dense():
+    from paper_2504_03967_amd import qg
+    old = qg.get_tuning("dense_min_gates")
+    qg.set_tuning("dense_min_gates", 1)
+    yield qg
+    qg.set_tuning("dense_min_gates", old)
+
+
+def local_circuit(n, k, n_gates, seed):
+    rng = W.SplitMix64(seed)
+    pool = rng.shuffle(range(n))[:k]
+    b = W.CircuitBuilder(n)
+    for q in range(n):
+        b.g1(W.H, q)
+    prep = b.build()
+    b = W.CircuitBuilder(n)
+    for _ in range(n_gates):
+        op = int(rng.below(10 if k > 1 else 6)[0])
+        t = pool[int(rng.below(k)[0])]
+        c = -1
+        if op >= W.CX:
+            c = pool[int(rng.below(k)[0])]
+            while c == t:
+                c = pool[int(rng.below(k)[0])]
+        b.add(op, c, t, 2 * math.pi * rng.uniform(3))
+    return prep, b.build()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,k", [(10, 4), (12, 5), (13, 6), (16, 3), (18, 5), (20, 6), (21, 2)])
+def test_dense_block_matches_oracle(qg_dense, n, k, dtype):
+    prep, circ = local_circuit(n, k, 40, seed=100 * n + k)
+    st = qg_dense.State(n, dtype)
+    st.apply(prep, qg_dense.FUSE_NONE)      # generic start state
+    st.apply(circ, qg_dense.FUSE_GREEDY)    # one pass on <= 6 qubits -> dense block
+    torch.cuda.synchronize()
+    psi = oracle.apply(circ, oracle.simulate(prep))
+    got = st.tensor.cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(got - psi)) < TOL[dtype]
+    st.close()
+
+
+def test_dense_in_a_full_circuit(qg_dense):
+    circ = W.config3(18, layers=6)
+    st = qg_dense.State(18, "c128")
+    st.apply(circ, qg_dense.FUSE_GREEDY)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(st.tensor.cpu().numpy() - oracle.simulate(circ))) < 1e-12
