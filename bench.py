@@ -37,11 +37,118 @@ def parse():
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--skip-cpu", action="store_true", help="omit the oracle CPU baseline")
-    ap.add_argument("--cpu-gates", type=int, default=8, help="sweep gates the oracle sample applies")
+    ap.add_argument("--cpu-gates", type=int, default=40, help="sweep parts the oracle sample applies")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 4 GiB device copy (reference kernel for HBM byte counters)")
     ap.add_argument("--parts-json", default="", help="write per-part timings to this file")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="omit the adjoint / batched speed-ups and the learned-fusion gain")
+    ap.add_argument("--cm-samples", type=int, default=1500, help="timed passes for the cost-model dataset")
     return ap.parse_args()
+
+
+def timed(fn, sync):
+    sync()
+    t0 = time.perf_counter()
+    r = fn()
+    sync()
+    return time.perf_counter() - t0, r
+
+
+def adjoint_speedup(qg, W, torch):
+    """Config 5: gradient of sum <Z_i Z_i+1> (24 qubits, 480 parameters) by one adjoint sweep
+    vs the plain method, central differences (960 forward simulations + expectations)."""
+    circ = W.config5()
+    n, npar = circ.n_qubits, circ.n_params
+    masks = W.zz_chain_masks(n)
+    coeffs = np.ones(n - 1)
+    qg.adjoint_grad(circ, masks, coeffs, npar)  # warm
+    t_adj, _ = timed(lambda: qg.adjoint_grad(circ, masks, coeffs, npar), torch.cuda.synchronize)
+    st = qg.State(n, "c128")
+    h = 1e-6
+    shifted = []
+    for k in range(npar):
+        (g,) = np.nonzero(circ.param_idx == k)
+        for sgn in (1, -1):
+            c = circ.copy()
+            c.gate_param[g, 0] += sgn * h
+            shifted.append(c)
+
+    def plain():
+        vals = []
+        for c in shifted:
+            st.reset()
+            st.apply(c, qg.FUSE_GREEDY)
+            vals.append(st.expval(masks, coeffs)[1])
+        return vals
+
+    st.apply(circ, qg.FUSE_GREEDY)
+    t_fd, _ = timed(plain, torch.cuda.synchronize)
+    st.close()
+    return {"workload": "24 qubits c128, 10-layer ansatz, 480 parameters, 710 gates",
+            "t_adjoint_s": round(t_adj, 4), "t_plain_fd_s": round(t_fd, 3),
+            "plain": "central differences, 960 greedy-fused forward passes + expval",
+            "speedup": round(t_fd / t_adj, 1)}
+
+
+def batched_speedup(qg, W, torch):
+    """Config 4: 4096 ansatz circuits (8..20 qubits) in one graph-replayed persistent launch
+    vs the plain loop (per circuit: reset, apply with one pass per gate, expval)."""
+    circs = W.config4()
+    stream = torch.cuda.Stream()
+    out = {"workload": "4096 ansatz circuits, 8..20 qubits, 2..12 layers, sum Z_i Z_i+1 each"}
+    amp_updates = float(sum(c.n_gates * (1 << c.n_qubits) for c in circs))
+    with torch.cuda.stream(stream):
+        for dtype in ("c128", "c64"):
+            b = qg.Batch(circs, dtype, stream=stream)
+            b.launch()
+            t_b, _ = timed(b.launch, stream.synchronize)
+            b.close()
+            out[f"t_batched_{dtype}_s"] = round(t_b, 4)
+            out[f"amp_updates_per_s_batched_{dtype}"] = amp_updates / t_b
+        states = {}
+        for n in sorted({c.n_qubits for c in circs}):
+            states[n] = qg.State(n, "c128", stream=stream)
+        zz = {n: W.zz_chain_masks(n) for n in states}
+
+        def plain():
+            for c in circs:
+                st = states[c.n_qubits]
+                st.reset()
+                st.apply(c, qg.FUSE_NONE)
+                st.expval(zz[c.n_qubits], np.ones(c.n_qubits - 1))
+
+        t_p, _ = timed(plain, stream.synchronize)
+        for st in states.values():
+            st.close()
+    out["t_plain_loop_c128_s"] = round(t_p, 3)
+    out["plain"] = "per-circuit qg_apply_circuit (one pass per gate) + qg_expval, c128"
+    out["speedup_c128"] = round(t_p / out["t_batched_c128_s"], 1)
+    return out
+
+
+def learned_gain(qg, W, torch, samples, log):
+    """Cost model trained on pass timings the simulator makes (library MLP kernels), then
+    measured time of greedy width-5 plans vs learned plans on held-out circuits."""
+    from paper_2504_03967_amd import costmodel as cm
+    t0 = time.perf_counter()
+    X, y = cm.collect(samples, n_values=(20, 22, 24, 26, 28), log=log)
+    t_collect = time.perf_counter() - t0
+    n_train = int(0.85 * len(y))
+    t1 = time.perf_counter()
+    model, losses = cm.train(X[:n_train], y[:n_train], epochs=300, batch=128, lr=2e-3)
+    t_train = time.perf_counter() - t1
+    err = cm.mape(model, X[n_train:], y[n_train:])
+    model.install()
+    circs = cm.held_out_circuits(count=20)
+    res = cm.compare_plans(circs)
+    qg.clear_cost_model()
+    model.close()
+    return {"samples": int(len(y)), "t_collect_s": round(t_collect, 1), "t_train_s": round(t_train, 2),
+            "train_loss_first_last": [round(float(losses[0]), 4), round(float(losses[-1]), 4)],
+            "heldout_mape": round(err, 3), "circuits": len(circs),
+            "t_greedy5_s": round(res["t_greedy_s"], 4), "t_learned_s": round(res["t_learned_s"], 4),
+            "gain": round(res["gain"], 3)}
 
 
 def log(msg):
@@ -165,8 +272,18 @@ def main():
         del psi
         cpu = {"value": sample.n_gates * (1 << n) / dt, "unit": "amp-updates/s", "cores": threads,
                "kind": "oracle",
-               "sample": f"first {sample.n_gates} gates of the {n}-qubit sweep (U3 on targets 0..{sample.n_gates - 1}) "
-                         f"on a 2^{n} complex128 state, {dt:.1f} s"}
+               "sample": f"first {sample.n_gates} gates of the {n}-qubit sweep on a 2^{n} complex128 state "
+                         f"(one FP64 pass per gate), {dt:.1f} s"}
+
+    extras = {}
+    if not args.no_extras:
+        log("adjoint vs finite differences (config 5)")
+        extras["adjoint"] = adjoint_speedup(qg, W, torch)
+        log(f"adjoint speedup {extras['adjoint']['speedup']}x; batched vs plain loop (config 4)")
+        extras["batched"] = batched_speedup(qg, W, torch)
+        log(f"batched speedup {extras['batched']['speedup_c128']}x; learned fusion")
+        extras["learned_fusion"] = learned_gain(qg, W, torch, args.cm_samples, log)
+        log(f"learned fusion gain {extras['learned_fusion']['gain']}")
 
     out = {
         "metric": "amp-updates/s (30q c128 gate sweep)",
@@ -191,6 +308,7 @@ def main():
         "sweep": sweep,
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     print(json.dumps(out))
 
 

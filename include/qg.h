@@ -64,9 +64,11 @@ typedef enum {
 /* Fusion modes of qg_apply_circuit. */
 typedef enum {
     QG_FUSE_NONE = 0,    /* one device pass per gate */
-    QG_FUSE_GREEDY = 1,  /* greedy fixed-width fusion: a pass holds consecutive gates whose
-                            non-diagonal targets span at most 5 qubits outside the low,
-                            always-resident tile qubits (the paper's gate fusion = 5, App. D.2) */
+    QG_FUSE_GREEDY = 1,  /* greedy fixed-width fusion: a pass holds gates whose non-diagonal
+                            targets span at most 5 qubits outside the low, always-resident
+                            tile qubits (the paper's gate fusion = 5, App. D.2); gates on
+                            disjoint qubits commute, so each pass takes every pending gate
+                            that fits and is not blocked by an earlier gate on its qubits */
     QG_FUSE_LEARNED = 2  /* cost-model planner (qg_mlp_*); falls back to greedy without a model */
 } qg_fusion;
 
@@ -186,7 +188,8 @@ qg_status qg_batch_free(qg_batch *b);
 /* Plan inspection (host only, no device needed): the pass each gate of the
  * circuit is executed in under fusion_mode, written to pass_of_gate[n_gates]
  * (host, may be NULL), and the pass count to *n_passes.  Passes run in
- * increasing order and cover every gate exactly once, in order. */
+ * increasing order and cover every gate exactly once; two gates that share a
+ * qubit run in circuit order. */
 qg_status qg_plan_passes(const qg_circuit *c, qg_dtype dtype, int fusion_mode,
                          int32_t *pass_of_gate, int32_t *n_passes);
 
@@ -217,17 +220,20 @@ qg_status qg_mlp_train(qg_mlp *m, const float *x, const float *t, int N, int epo
                        uint64_t seed, double *loss_per_epoch);
 qg_status qg_mlp_free(qg_mlp *m);
 
-/* Number of features of a candidate pass, and the candidate fusion
- * configurations: config k allows 4 + k required qubits outside the low
- * block (k = 1 is the greedy default, width 5). */
+/* Number of features of a candidate pass, and the candidate strategies:
+ * config k < QG_PASS_DENSE is a tile pass allowing 4 + k required qubits
+ * outside the low block (k = 1 is the greedy default, width 5); config
+ * QG_PASS_DENSE is a dense block on the matrix cores. */
 #define QG_PASS_FEATURES 24
-#define QG_PASS_CONFIGS 4
+#define QG_PASS_CONFIGS 5
+#define QG_PASS_DENSE 4
 /* Features of the whole circuit run as one pass under candidate config k
  * (features[QG_PASS_FEATURES], host); *n_passes (may be NULL) receives the
- * number of passes the greedy rule of that config would form. */
+ * number of passes the greedy rule of that config would form (1 for the
+ * dense strategy, which needs n >= 8 and at most 6 touched qubits). */
 qg_status qg_pass_features(const qg_circuit *c, qg_dtype dtype, int config, float *features, int32_t *n_passes);
 /* Installs the model QG_FUSE_LEARNED plans with (NULL: greedy fallback).  The
- * learned planner prices candidate passes (each start gate, each config)
+ * learned planner prices candidate passes (each start gate, each strategy)
  * with one batched forward of the model, predicting ln(pass time in
  * microseconds), and keeps the partition of least predicted total time (dynamic
  * programming); plans are cached per circuit structure.  The model must have
@@ -236,6 +242,8 @@ qg_status qg_set_cost_model(qg_mlp *m);
 
 /* Process-wide planner tuning (not part of the paper's method; performance only,
  * results are identical up to rounding for every setting).  Keys:
+ *   dense_min_gates                  a greedy pass touching <= 6 qubits with at least
+ *                                    this many gates runs as a dense MFMA block
  *   tile_bits_c128 / tile_bits_c64   qubits per tile (amplitudes streamed per workgroup)
  *   reg_bits_c128 / reg_bits_c64     amplitudes per thread = 2^reg_bits
  *   low_bits_c128 / low_bits_c64     lowest qubits kept in every fused tile

@@ -42,9 +42,11 @@ def restore(prev: Dict[str, int]) -> None:
         qg.set_tuning(key, v)
 
 
-def random_gates(n: int, n_gates: int, rng: W.SplitMix64, ops: Sequence[int] = tuple(range(10))) -> W.Circuit:
+def random_gates(n: int, n_gates: int, rng: W.SplitMix64, ops: Sequence[int] = tuple(range(10)),
+                 max_pool: int = 0) -> W.Circuit:
     """Random gate list on a random subset of the qubits (locality varies per call)."""
-    size = 2 + int(rng.below(n - 1)[0])
+    top = n if max_pool <= 0 else min(n, max_pool)
+    size = 2 + int(rng.below(top - 1)[0])
     pool = rng.shuffle(range(n))[:size]
     b = W.CircuitBuilder(n)
     for _ in range(n_gates):
@@ -66,9 +68,9 @@ def first_pass(circ: W.Circuit, dtype: str, k: int) -> W.Circuit:
         pog, _ = qg.plan_passes(circ, dtype, qg.FUSE_GREEDY)
     finally:
         restore(prev)
-    g = int(np.sum(pog == 0))
-    return W.Circuit(circ.n_qubits, circ.gate_type[:g].copy(), circ.gate_param[:g].copy(),
-                     np.full(g, -1, np.int32))
+    sel = pog == 0
+    return W.Circuit(circ.n_qubits, circ.gate_type[sel].copy(), circ.gate_param[sel].copy(),
+                     np.full(int(sel.sum()), -1, np.int32))
 
 
 def time_apply(st: "qg.State", circ: W.Circuit, fusion: int, reps: int = 3) -> float:
@@ -100,18 +102,26 @@ def collect(n_samples: int, n_values: Sequence[int] = (20, 22, 24, 26, 28),
         dtype = dtypes[int(rng.below(len(dtypes))[0])]
         k = int(rng.below(qg.PASS_CONFIGS)[0])
         G = 1 + int(rng.below(80)[0])
-        block = first_pass(random_gates(n, G, rng), dtype, k)
+        if k == qg.PASS_DENSE:
+            # a run on at most 6 qubits, executed as one dense block
+            block = random_gates(n, G, rng, max_pool=6)
+        else:
+            block = first_pass(random_gates(n, G, rng), dtype, k)
         f, npass = qg.pass_features(block, dtype, k)
         assert npass == 1
         key = (n, dtype)
         if key not in states:
             states[key] = qg.State(n, dtype)
             states[key].apply(W.uniform_superposition(n), qg.FUSE_GREEDY)
-        prev = set_config(dtype, k)
+        prev = set_config(dtype, 3 if k == qg.PASS_DENSE else k)
+        prev_dense = qg.get_tuning("dense_min_gates")
+        if k == qg.PASS_DENSE:
+            qg.set_tuning("dense_min_gates", 1)
         try:
             t = time_apply(states[key], block, qg.FUSE_GREEDY, reps)
         finally:
             restore(prev)
+            qg.set_tuning("dense_min_gates", prev_dense)
         X.append(f)
         y.append(math.log(t * 1e6))
         if log and (s + 1) % 200 == 0:

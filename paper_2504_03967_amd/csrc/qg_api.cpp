@@ -292,10 +292,10 @@ Program plan_batch_circuit(const qg_circuit &q, bool c64) {
     const int rb = c64 ? 5 : 4;
     w.n_qubits = std::max(q.n_qubits, rb);
     PlanConfig cfg = batch_config(w.n_qubits, c64);
-    std::vector<Gate> gl = load_gates(&w);
-    std::vector<PassRange> ranges = fuse(gl, cfg);
-    if (ranges.empty()) ranges.push_back({0, 0});  // identity pass keeps control flow uniform
-    return build_program(gl, ranges, cfg);
+    const std::vector<Gate> gl0 = load_gates(&w);
+    Schedule sc = schedule(gl0, cfg);
+    if (sc.ranges.empty()) sc.ranges.push_back({0, 0});  // identity pass keeps control flow uniform
+    return build_program(permute(gl0, sc.order), sc.ranges, cfg);
 }
 
 struct BatchDev {
@@ -496,7 +496,8 @@ hipError_t mlp_act(qg_mlp *M, int B, int loss_slots, MlpAct *a) {
 }
 
 qg_mlp *g_cost_model = nullptr;
-static_assert(kPlanFeatures == QG_PASS_FEATURES && kPlanConfigs == QG_PASS_CONFIGS, "feature layout");
+static_assert(kPlanFeatures == QG_PASS_FEATURES && kPlanConfigs == QG_PASS_CONFIGS && kPlanDense == QG_PASS_DENSE,
+              "feature layout");
 
 }  // namespace
 
@@ -505,8 +506,9 @@ namespace {
 // ---- learned fusion: dynamic programming over candidate passes priced by the cost model
 
 struct PlanEntry {
-    std::vector<PassRange> ranges;
-    std::vector<int> cfg;   // candidate configuration index per pass
+    std::vector<int> order;         // execution order of the gates (commutation-aware schedule)
+    std::vector<PassRange> ranges;  // passes over `order`
+    std::vector<int> cfg;           // candidate strategy index per pass
 };
 
 std::mutex g_plan_mu;
@@ -529,23 +531,25 @@ uint64_t structure_hash(int n, bool c64, const std::vector<Gate> &g) {
     return h;
 }
 
-qg_status learned_plan(const std::vector<Gate> &g, int n, bool c64, PlanEntry *out) {
-    const int G = (int)g.size();
+qg_status learned_plan(const std::vector<Gate> &g0, int n, bool c64, PlanEntry *out) {
+    const int G = (int)g0.size();
     out->ranges.clear();
     out->cfg.clear();
+    Schedule sc = schedule(g0, candidate_config(n, c64, 1));
+    out->order = sc.order;
     if (!g_cost_model) {
-        PlanConfig cfg = candidate_config(n, c64, 1);
-        out->ranges = fuse(g, cfg);
+        out->ranges = sc.ranges;
         out->cfg.assign(out->ranges.size(), 1);
         return QG_OK;
     }
+    const std::vector<Gate> g = permute(g0, sc.order);
     {
         std::lock_guard<std::mutex> lk(g_plan_mu);
         if (g_plan_cache_model != g_cost_model) {
             g_plan_cache.clear();
             g_plan_cache_model = g_cost_model;
         }
-        auto it = g_plan_cache.find(structure_hash(n, c64, g));
+        auto it = g_plan_cache.find(structure_hash(n, c64, g0));
         if (it != g_plan_cache.end()) {
             *out = it->second;
             return QG_OK;
@@ -559,14 +563,21 @@ qg_status learned_plan(const std::vector<Gate> &g, int n, bool c64, PlanEntry *o
     PlanConfig cfgs[kPlanConfigs];
     for (int k = 0; k < kPlanConfigs; ++k) cfgs[k] = candidate_config(n, c64, k);
     for (int i = 0; i < G; ++i) {
-        int last_j = -1;
         for (int k = 0; k < kPlanConfigs; ++k) {
-            const int j = first_block_end(g, i, cfgs[k]);
-            (void)last_j;
+            int j;
+            if (k == kPlanDense) {
+                j = dense_block_end(g, i, 4096);
+                const uint64_t blk = j > i ? dense_block_qubits(g, i, j, n) : 0;
+                if (!blk) continue;
+                cand.push_back({i, j, k});
+                feat.resize(feat.size() + kPlanFeatures);
+                dense_features(g, i, j, blk, cfgs[1], feat.data() + feat.size() - kPlanFeatures);
+                continue;
+            }
+            j = first_block_end(g, i, cfgs[k]);
             cand.push_back({i, j, k});
             feat.resize(feat.size() + kPlanFeatures);
             pass_features(g, i, j, cfgs[k], feat.data() + feat.size() - kPlanFeatures);
-            last_j = j;
         }
     }
     std::vector<float> pred(cand.size());
@@ -574,11 +585,11 @@ qg_status learned_plan(const std::vector<Gate> &g, int n, bool c64, PlanEntry *o
     if (st != QG_OK) return st;
     std::vector<double> best(G + 1, 0.0);
     std::vector<int> choice(G, -1);
-    // candidates are grouped by start i (kPlanConfigs each)
+    std::vector<int> first(G + 1, (int)cand.size());
+    for (int c = (int)cand.size() - 1; c >= 0; --c) first[cand[c].i] = c;
     for (int i = G - 1; i >= 0; --i) {
         double b = 1e300;
-        for (int k = 0; k < kPlanConfigs; ++k) {
-            const int c = i * kPlanConfigs + k;
+        for (int c = first[i]; c < (int)cand.size() && cand[c].i == i; ++c) {
             const double v = std::exp((double)pred[c]) + best[cand[c].j];
             if (v < b) {
                 b = v;
@@ -594,13 +605,20 @@ qg_status learned_plan(const std::vector<Gate> &g, int n, bool c64, PlanEntry *o
         i = c.j;
     }
     std::lock_guard<std::mutex> lk(g_plan_mu);
-    g_plan_cache[structure_hash(n, c64, g)] = *out;
+    g_plan_cache[structure_hash(n, c64, g0)] = *out;
     return QG_OK;
 }
 
-Program build_learned(const std::vector<Gate> &g, const PlanEntry &e, int n, bool c64) {
+Program build_learned(const std::vector<Gate> &g0, const PlanEntry &e, int n, bool c64) {
+    const std::vector<Gate> g = permute(g0, e.order);
     Program prog;
     for (size_t p = 0; p < e.ranges.size(); ++p) {
+        if (e.cfg[p] == kPlanDense) {
+            const PassRange &r = e.ranges[p];
+            append_dense(&prog, g, r.g_begin, r.g_end, dense_block_qubits(g, r.g_begin, r.g_end, n),
+                         candidate_config(n, c64, 1));
+            continue;
+        }
         PlanConfig cfg = candidate_config(n, c64, e.cfg[p]);
         std::vector<PassRange> one{e.ranges[p]};
         append_program(&prog, build_program(g, one, cfg));
@@ -701,18 +719,22 @@ qg_status qg_plan_passes(const qg_circuit *c, qg_dtype dtype, int fusion_mode, i
     if (dtype != QG_C64 && dtype != QG_C128) return fail(QG_EINVAL, "unknown dtype %d", (int)dtype);
     std::vector<Gate> g = load_gates(c);
     std::vector<PassRange> r;
+    std::vector<int> order;
     if (fusion_mode == QG_FUSE_LEARNED) {
         PlanEntry e;
         qg_status st = learned_plan(g, c->n_qubits, dtype == QG_C64, &e);
         if (st != QG_OK) return st;
         r = e.ranges;
+        order = e.order;
     } else {
         PlanConfig cfg = plan_config(c->n_qubits, dtype == QG_C64, fusion_mode);
-        r = fuse(g, cfg);
+        Schedule sc = schedule(g, cfg);
+        order = sc.order;
+        r = sc.ranges;
     }
     for (size_t p = 0; p < r.size(); ++p)
         for (int i = r[p].g_begin; i < r[p].g_end; ++i)
-            if (pass_of_gate) pass_of_gate[i] = (int32_t)p;
+            if (pass_of_gate) pass_of_gate[order.empty() ? i : order[i]] = (int32_t)p;
     if (n_passes) *n_passes = (int32_t)r.size();
     return QG_OK;
 }
@@ -837,7 +859,7 @@ qg_status qg_adjoint_grad(const qg_circuit *c, qg_dtype dtype, const uint64_t *z
     // Forward sweep
     HIP_TRY(launch_zero_state(c64, psi, dim, cx.stream), "state init");
     PlanConfig fcfg = plan_config(n, c64, QG_FUSE_GREEDY);
-    Program fwd = build_program(g, fuse(g, fcfg), fcfg);
+    Program fwd = build_plan(g, fcfg);
     st = run_program(cx, c64, fwd, psi, nullptr, nullptr);
     if (st != QG_OK) return st;
     // f and lambda = O psi
@@ -878,7 +900,7 @@ qg_status qg_adjoint_grad(const qg_circuit *c, qg_dtype dtype, const uint64_t *z
     rcfg.reverse = true;
     clamp_config(&rcfg);
     std::vector<Gate> rg = execution_order(g, true);
-    Program rev = build_program(rg, fuse(rg, rcfg), rcfg);
+    Program rev = build_plan(rg, rcfg);
     const int n_rows = (int)rev.grad_row_slot.size();
     HIP_TRY(cx.work2.ensure((n_rows + 1) * sizeof(double) + (n_rows + 1) * sizeof(int32_t) + 512, cx.stream),
             "gradient rows");
@@ -1202,6 +1224,13 @@ qg_status qg_pass_features(const qg_circuit *c, qg_dtype dtype, int config, floa
     if (!features) return fail(QG_EINVAL, "features is NULL");
     if (c->n_gates < 1) return fail(QG_EINVAL, "empty circuit");
     std::vector<Gate> g = load_gates(c);
+    if (config == kPlanDense) {
+        const uint64_t blk = dense_block_qubits(g, 0, (int)g.size(), c->n_qubits);
+        if (!blk) return fail(QG_EINVAL, "a dense block needs n >= 8 and at most 6 touched qubits");
+        if (n_passes) *n_passes = 1;
+        dense_features(g, 0, (int)g.size(), blk, candidate_config(c->n_qubits, dtype == QG_C64, 1), features);
+        return QG_OK;
+    }
     PlanConfig cfg = candidate_config(c->n_qubits, dtype == QG_C64, config);
     if (n_passes) *n_passes = (int32_t)fuse(g, cfg).size();
     pass_features(g, 0, (int)g.size(), cfg, features);

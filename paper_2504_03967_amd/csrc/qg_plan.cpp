@@ -331,6 +331,58 @@ std::vector<PassRange> fuse(const std::vector<Gate> &g, const PlanConfig &cfg) {
     return out;
 }
 
+Schedule schedule(const std::vector<Gate> &g, const PlanConfig &cfg) {
+    Schedule sc;
+    const int G = (int)g.size();
+    if (cfg.fusion == QG_FUSE_NONE || G == 0) {
+        for (int i = 0; i < G; ++i) sc.order.push_back(i);
+        sc.ranges = fuse(g, cfg);
+        return sc;
+    }
+    const int n = cfg.n;
+    const int b = std::min(n, cfg.tile_bits);
+    const int low = n <= b ? n : std::min(cfg.low_bits, b);
+    const uint64_t low_mask = low >= 64 ? ~0ull : ((1ull << low) - 1);
+    const int max_high = n <= b ? 64 : std::min(cfg.max_high, b - low);
+    std::vector<int> pending(G);
+    for (int i = 0; i < G; ++i) pending[i] = i;
+    const int kMaxGradPerPass = 64;  // bounds the adjoint partial-sum scratch
+    while (!pending.empty()) {
+        uint64_t high = 0, blocked = 0;
+        int taken = 0, grads = 0;
+        std::vector<int> rest;
+        rest.reserve(pending.size());
+        const int begin = (int)sc.order.size();
+        for (int idx : pending) {
+            const Gate &x = g[idx];
+            const uint64_t touch = touched_qubits(x);
+            const uint64_t req = required_qubits(x) & ~low_mask;
+            const bool ready = (touch & blocked) == 0;
+            const int gr = (cfg.reverse && x.pidx >= 0) ? 1 : 0;
+            if (ready && taken < cfg.max_gates_per_pass && grads + gr <= kMaxGradPerPass &&
+                popcount64(high | req) <= max_high) {
+                high |= req;
+                sc.order.push_back(idx);
+                ++taken;
+                grads += gr;
+            } else {
+                blocked |= touch;
+                rest.push_back(idx);
+            }
+        }
+        sc.ranges.push_back({begin, (int)sc.order.size()});
+        pending.swap(rest);
+    }
+    return sc;
+}
+
+std::vector<Gate> permute(const std::vector<Gate> &g, const std::vector<int> &order) {
+    std::vector<Gate> out;
+    out.reserve(order.size());
+    for (int i : order) out.push_back(g[i]);
+    return out;
+}
+
 Program build_program(const std::vector<Gate> &gates, const std::vector<PassRange> &ranges,
                       const PlanConfig &cfg) {
     Program prog;
@@ -586,8 +638,11 @@ void append_dense(Program *prog, const std::vector<Gate> &g, int begin, int end,
     prog->passes.push_back(pd);
 }
 
-Program build_plan(const std::vector<Gate> &g, const PlanConfig &cfg) {
-    std::vector<PassRange> ranges = fuse(g, cfg);
+Program build_plan(const std::vector<Gate> &g0, const PlanConfig &cfg, std::vector<int> *order) {
+    Schedule sc = schedule(g0, cfg);
+    if (order) *order = sc.order;
+    const std::vector<Gate> g = permute(g0, sc.order);
+    const std::vector<PassRange> &ranges = sc.ranges;
     if (cfg.dense_min_gates >= (1 << 30) || cfg.reverse || cfg.n < 8) return build_program(g, ranges, cfg);
     Program prog;
     prog.pass_of_gate.assign(g.size(), -1);
@@ -679,7 +734,7 @@ void pass_features(const std::vector<Gate> &g, int begin, int end, const PlanCon
     f[4] = sub.size() / 32.f;
     f[5] = p.ops.size() / 32.f;
     f[6] = pd.n_phase / 8.f;
-    f[7] = (pd.n_phase - 1) / 8.f;
+    f[7] = 0.f;  // strategy: tile pass
     f[8] = popcount64(req) / 8.f;
     f[9] = popcount64(req & ~low_mask) / 8.f;
     f[10] = pd.b / 16.f;
@@ -687,6 +742,46 @@ void pass_features(const std::vector<Gate> &g, int begin, int end, const PlanCon
     f[12] = cfg.low_bits / 16.f;
     f[13] = cfg.max_high / 8.f;
     for (int k = 0; k < 10; ++k) f[14 + k] = counts[k] / 16.f;
+}
+
+void dense_features(const std::vector<Gate> &g, int begin, int end, uint64_t blk, const PlanConfig &cfg, float *f) {
+    int counts[10] = {0};
+    uint64_t req = 0;
+    for (int i = begin; i < end; ++i) {
+        counts[g[i].op]++;
+        req |= required_qubits(g[i]);
+    }
+    const int k = popcount64(blk);
+    const int l = std::min(std::min(cfg.n, cfg.tile_bits) - k, cfg.n - k);
+    const int sbits = cfg.c64 ? 3 : 4;
+    const uint64_t low_mask = cfg.low_bits >= 64 ? ~0ull : ((1ull << cfg.low_bits) - 1);
+    f[0] = cfg.n / 32.f;
+    f[1] = cfg.c64 ? 0.f : 1.f;
+    f[2] = 0.f;
+    f[3] = (cfg.n + sbits + 1 - 30) / 4.f;
+    f[4] = (end - begin) / 32.f;
+    f[5] = (end - begin) / 32.f;
+    f[6] = 1 / 8.f;
+    f[7] = 1.f;  // strategy: dense block
+    f[8] = k / 8.f;
+    f[9] = popcount64(blk & ~low_mask) / 8.f;
+    f[10] = (k + l) / 16.f;
+    f[11] = 0.f;
+    f[12] = l / 16.f;
+    f[13] = k / 8.f;
+    for (int j = 0; j < 10; ++j) f[14 + j] = counts[j] / 16.f;
+    (void)req;
+}
+
+int dense_block_end(const std::vector<Gate> &g, int begin, int max_gates) {
+    uint64_t q = 0;
+    int i = begin;
+    for (; i < (int)g.size() && i - begin < max_gates; ++i) {
+        const uint64_t nq = q | touched_qubits(g[i]);
+        if (popcount64(nq) > 6) break;
+        q = nq;
+    }
+    return i;
 }
 
 }  // namespace qg

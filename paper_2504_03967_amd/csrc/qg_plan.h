@@ -79,8 +79,19 @@ std::vector<Gate> load_gates(const qg_circuit *c);
 // Execution-order gate list (reversed for adjoint sweeps).
 std::vector<Gate> execution_order(const std::vector<Gate> &g, bool reverse);
 
-// Fusion: partition execution-order gates into passes.
+// Fusion: partition execution-order gates into passes, in order.
 std::vector<PassRange> fuse(const std::vector<Gate> &g, const PlanConfig &cfg);
+
+// Commutation-aware greedy fusion: gates touching disjoint qubits commute, so a
+// pass takes, in one scan, every not-yet-scheduled gate that fits its width and
+// is not preceded by a skipped gate sharing one of its qubits.  `order` lists
+// gate indices in execution order; ranges index into `order`.
+struct Schedule {
+    std::vector<int> order;
+    std::vector<PassRange> ranges;
+};
+Schedule schedule(const std::vector<Gate> &g, const PlanConfig &cfg);
+std::vector<Gate> permute(const std::vector<Gate> &g, const std::vector<int> &order);
 
 // Device program for the given pass partition.
 Program build_program(const std::vector<Gate> &g, const std::vector<PassRange> &passes,
@@ -93,22 +104,28 @@ uint64_t touched_qubits(const Gate &g);
 void append_dense(Program *prog, const std::vector<Gate> &g, int begin, int end, uint64_t blk, const PlanConfig &cfg);
 // Block qubits for a dense step of gates [begin, end), or 0 if they touch more than 6 qubits.
 uint64_t dense_block_qubits(const std::vector<Gate> &g, int begin, int end, int n);
-// Greedy plan with the dense rule applied (cfg.dense_min_gates).
-Program build_plan(const std::vector<Gate> &g, const PlanConfig &cfg);
+// Greedy plan (commutation-aware schedule) with the dense rule applied (cfg.dense_min_gates).
+// *order (may be NULL) receives the execution order of the gates.
+Program build_plan(const std::vector<Gate> &g, const PlanConfig &cfg, std::vector<int> *order = nullptr);
 
 // Appends a program's passes, phases and ops (offsetting their indices); pass_of_gate is not merged.
 void append_program(Program *dst, const Program &src);
 
 // ---- learned fusion: features of one candidate pass
 constexpr int kPlanFeatures = 24;
-// Candidate (low_bits, max_high) fusion configurations per dtype; index 1 is the
-// greedy default (width 5).
-constexpr int kPlanConfigs = 4;
+// Candidate strategies: k = 0..3 are tile passes with max_high = 4 + k (index 1 is
+// the greedy default, width 5); k = kPlanDense is a dense block on the matrix cores.
+constexpr int kPlanConfigs = 5;
+constexpr int kPlanDense = 4;
 PlanConfig candidate_config(int n, bool c64, int k);
 // End of the pass the greedy rule would form starting at gate `begin`.
 int first_block_end(const std::vector<Gate> &g, int begin, const PlanConfig &cfg);
 // Features of gates [begin, end) executed as one pass under cfg (scaled, see the .cpp).
 void pass_features(const std::vector<Gate> &g, int begin, int end, const PlanConfig &cfg, float *f);
+// Features of gates [begin, end) executed as one dense block on qubits blk.
+void dense_features(const std::vector<Gate> &g, int begin, int end, uint64_t blk, const PlanConfig &cfg, float *f);
+// End of the longest run from `begin` whose gates touch at most 6 qubits (and at most max_gates).
+int dense_block_end(const std::vector<Gate> &g, int begin, int max_gates);
 
 // 2x2 matrix of a single-qubit gate (textbook forms, header of qg.h).
 void gate_matrix(int op, const double *p, cd m[2][2]);

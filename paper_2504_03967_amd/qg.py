@@ -30,7 +30,8 @@ EXPORTS = (
     "qg_mlp_grad", "qg_mlp_adam_step", "qg_mlp_train", "qg_mlp_free", "qg_pass_features", "qg_set_cost_model",
 )
 PASS_FEATURES = 24
-PASS_CONFIGS = 4
+PASS_CONFIGS = 5
+PASS_DENSE = 4
 
 
 class QGError(RuntimeError):
