@@ -17,7 +17,8 @@ using namespace dev;
 
 __device__ __forceinline__ double zz_chain(uint64_t i, int n) {
     const uint64_t mask = n >= 2 ? ((1ull << (n - 1)) - 1) : 0;
-    return (double)((n - 1) - 2 * __popcll((i ^ (i >> 1)) & mask));
+    // __popcll is unsigned: convert before subtracting
+    return (double)(n - 1) - 2.0 * (double)__popcll((i ^ (i >> 1)) & mask);
 }
 
 __global__ void k_batch_reset(int *counter) {

@@ -19,12 +19,16 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <typename R> struct Mfma;
+// Operand layout of both 16x16x4 forms: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16].  Output: lane l, register r holds D[row(l / 16, r)][l % 16]
+// (measured on gfx950: rows l/16 + 4 r for f64, 4 (l/16) + r for f32).
 template <> struct Mfma<double> {
     using C = double2;
     using Acc = d4;
     static __device__ __forceinline__ Acc mac(double a, double b, Acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
 };
 template <> struct Mfma<float> {
     using C = float2;
@@ -32,6 +36,7 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ Acc mac(float a, float b, Acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
 };
 
 // Global index offset of the low-bit pattern `v` over the qubit list q[0..cnt).
@@ -112,7 +117,7 @@ k_dense(const DenseDesc D, const R *__restrict__ ut_re, const R *__restrict__ ut
         }
     }
     __syncthreads();
-    // D fragment: lane holds rows 16 I + 4 (lane / 16) + r, column 16 J + lane % 16.
+    // D fragment: lane holds rows 16 I + row(lane / 16, r), column 16 J + lane % 16.
 #pragma unroll
     for (int q = 0; q < kMaxBlk; ++q) {
         const int blk = wave + 4 * q;
@@ -123,7 +128,7 @@ k_dense(const DenseDesc D, const R *__restrict__ ut_re, const R *__restrict__ ut
                 C y;
                 y.x = accr[q][r];
                 y.y = acci[q][r];
-                X[(16 * I + 4 * lk + r) * COLS + 16 * J + li] = y;
+                X[(16 * I + Mfma<R>::row(lk, r)) * COLS + 16 * J + li] = y;
             }
         }
     }

@@ -265,7 +265,7 @@ __device__ __forceinline__ double tile_obs_zz_chain(const PassDesc &P, const Pha
     for (int e = 0; e < (1 << RB); ++e) {
         const uint64_t i = gbase | tg | elem_goff<RB>(ph, e);
         const double p = (double)a[0][e].x * a[0][e].x + (double)a[0][e].y * a[0][e].y;
-        acc += p * (double)((n - 1) - 2 * __popcll((i ^ (i >> 1)) & mask));
+        acc += p * ((double)(n - 1) - 2.0 * (double)__popcll((i ^ (i >> 1)) & mask));
     }
     return acc;
 }

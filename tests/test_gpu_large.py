@@ -1,0 +1,96 @@
+"""Full-size checks where the oracle cannot run (32 GiB and 128 GiB states): properties
+that hold at any size — norm conservation, mirror circuits, the QFT closed form on
+basis states, GHZ, Porter-Thomas statistics of random circuits and of their shots."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2504_03967_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(31, "c128"), (32, "c64")]
+TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def qg():
+    from paper_2504_03967_amd import qg as lib
+    assert torch.cuda.is_available()
+    return lib
+
+
+@pytest.fixture(autouse=True)
+def free_memory():
+    yield
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,dtype", CASES)
+def test_config3_norm_porter_thomas_and_shots(qg, n, dtype):
+    circ = W.config3(n)
+    st = qg.State(n, dtype)
+    st.apply(circ, qg.FUSE_GREEDY)
+    terms, _ = st.expval([0, 1 | (1 << (n - 1))])
+    t = terms.cpu().numpy()
+    assert abs(t[0] - 1) < TOL[dtype]
+    assert -1 <= t[1] <= 1
+    N = float(1 << n)
+    p = st.probs(W.config3_indices(n)).cpu().numpy() * N
+    assert abs(p.mean() - 1) < 0.15 and abs((p * p).mean() - 2) < 0.5
+    # shots are size-biased: E[2^n p(shot)] = E[(2^n p)^2] / E[2^n p] = 2 for Porter-Thomas
+    shots = st.sample(20000, W.SEED_BASE + 2).cpu().numpy().astype(np.uint64)
+    ps = st.probs(shots).cpu().numpy() * N
+    assert np.all(ps > 0) and abs(ps.mean() - 2) < 0.15
+    st.close()
+
+
+@pytest.mark.parametrize("n,dtype", CASES)
+def test_mirror_circuit_returns_to_zero(qg, n, dtype):
+    circ = W.config3(n, layers=30)
+    full = W.concat(circ, W.inverse(circ))
+    st = qg.State(n, dtype)
+    st.apply(full, qg.FUSE_GREEDY)
+    a0 = st.tensor[0].item()
+    assert abs(a0 - 1) < TOL[dtype]
+    st.close()
+
+
+@pytest.mark.parametrize("n,dtype", CASES)
+def test_qft_of_basis_state_closed_form(qg, n, dtype):
+    x = int(W.SplitMix64(n).next_u64(1)[0] % np.uint64(1 << n))
+    b = W.CircuitBuilder(n)
+    for q in range(n):
+        if (x >> q) & 1:
+            b.g1(W.X, q)
+    W.qft(n, b)
+    st = qg.State(n, dtype)
+    st.apply(b.build(), qg.FUSE_GREEDY)
+    N = 1 << n
+    ks = np.concatenate([np.arange(64), W.config3_indices(n, seed=7, count=4000).astype(np.int64)])
+    got = st.tensor[torch.as_tensor(ks, device="cuda")].cpu().numpy().astype(np.complex128)
+    phase = ((x * ks.astype(object)) % N).astype(np.float64) / N  # exact integer product mod N
+    expect = np.exp(2j * np.pi * phase) / math.sqrt(N)
+    assert np.max(np.abs(got - expect)) < TOL[dtype]
+    st.close()
+
+
+@pytest.mark.parametrize("n,dtype", [(33, "c128"), (34, "c64")])
+def test_ghz_at_maximum_size(qg, n, dtype):
+    free, _ = torch.cuda.mem_get_info()
+    if free < (1 << n) * (16 if dtype == "c128" else 8) + (8 << 30):
+        pytest.skip("not enough free device memory for the maximum-size state")
+    st = qg.State(n, dtype)
+    st.apply(W.ghz(n), qg.FUSE_GREEDY)
+    idx = [0, (1 << n) - 1, 1, 1 << (n - 1), 12345678901 % (1 << n)]
+    p = st.probs(idx).cpu().numpy()
+    tol = 1e-13 if dtype == "c128" else 1e-6
+    assert abs(p[0] - 0.5) < tol and abs(p[1] - 0.5) < tol and np.all(np.abs(p[2:]) < tol)
+    terms, _ = st.expval([1 | (1 << (n - 1)), 1 << 5])
+    t = terms.cpu().numpy()
+    assert abs(t[0] - 1) < tol and abs(t[1]) < tol
+    st.close()
+    del st
