@@ -248,7 +248,8 @@ qg_status qg_set_cost_model(qg_mlp *m);
  *   reg_bits_c128 / reg_bits_c64     amplitudes per thread = 2^reg_bits
  *   low_bits_c128 / low_bits_c64     lowest qubits kept in every fused tile
  *   max_high_c128 / max_high_c64     fusion width: targets >= low_bits per pass
- *   nt                               1 = non-temporal state loads/stores
+ *   nt                               non-temporal state loads/stores: 0 off, 1 when every
+ *                                    wavefront access covers whole cache lines, 2 always
  *   swz_bits                         tile-order swizzle of the launch
  * Errors: QG_EINVAL for an unknown key or a value out of range.  Not
  * thread-safe against concurrent planning. */

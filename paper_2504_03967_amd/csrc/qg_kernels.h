@@ -53,6 +53,9 @@ hipError_t launch_grad_slots(const double *rows, const int32_t *row_slot, int n_
 hipError_t launch_dense(bool c64, const DenseDesc &D, const void *ut_re, const void *ut_im, void *psi,
                         hipStream_t st);
 
+// SWAP of qubits a and b as a permutation of the amplitudes whose bits differ.
+hipError_t launch_swap2(bool c64, void *psi, int n, int a, int b, hipStream_t st);
+
 // Batched persistent launch (all pointers are device pointers).
 struct BatchLaunch {
     const BatchCirc *circs;

@@ -145,7 +145,7 @@ const Knob kKnobs[] = {
     {"low_bits_c64", [](Tuning &t) { return &t.low_bits[1]; }, 0, 14},
     {"max_high_c128", [](Tuning &t) { return &t.max_high[0]; }, 1, 13},
     {"max_high_c64", [](Tuning &t) { return &t.max_high[1]; }, 1, 14},
-    {"nt", [](Tuning &t) { return &t.nt; }, 0, 1},
+    {"nt", [](Tuning &t) { return &t.nt; }, 0, 2},
     {"swz_bits", [](Tuning &t) { return &t.swz_bits; }, 0, 16},
     {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 1, 1 << 30},
 };
@@ -184,6 +184,7 @@ PlanConfig default_config(int n, bool c64, int fusion) {
     c.low_bits = std::min(t.low_bits[d], c.tile_bits);
     c.max_high = std::max(1, std::min(t.max_high[d], c.tile_bits - c.low_bits));
     c.flags = t.nt ? PASS_NT : 0;
+    c.nt_mode = t.nt;
     c.swz_bits = t.swz_bits;
     c.dense_min_gates = t.dense_min_gates;
     return c;
@@ -517,6 +518,19 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
             first = false;
         }
         pd.n_phase = (int)prog.phases.size() - pd.phase_begin;
+        // Non-temporal state accesses only pay when every wavefront load/store
+        // covers whole 128-byte lines: the first and last layouts must keep the
+        // line-offset tile positions (3 for complex128, 4 for complex64) on lanes.
+        if ((pd.flags & PASS_NT) && cfg.nt_mode == 1) {
+            const int line_bits = cfg.c64 ? 4 : 3;
+            const uint32_t line_mask = (1u << std::min(line_bits, b)) - 1;
+            for (int which : {pd.phase_begin, pd.phase_begin + pd.n_phase - 1}) {
+                const PhaseDesc &ph = prog.phases[which];
+                for (int j = 0; j < rb; ++j)
+                    if (ph.reg_poff[j] & line_mask) pd.flags &= ~PASS_NT;
+                if (tb < line_bits) pd.flags &= ~PASS_NT;
+            }
+        }
         pd.grad_base = grad_base;
         pd.n_grad = grad_rows - grad_base;
         const int64_t waves = std::max(1, (1 << tb) / 64);
@@ -643,12 +657,32 @@ Program build_plan(const std::vector<Gate> &g0, const PlanConfig &cfg, std::vect
     if (order) *order = sc.order;
     const std::vector<Gate> g = permute(g0, sc.order);
     const std::vector<PassRange> &ranges = sc.ranges;
-    if (cfg.dense_min_gates >= (1 << 30) || cfg.reverse || cfg.n < 8) return build_program(g, ranges, cfg);
+    const int line_bits = cfg.c64 ? 4 : 3;
+    bool special = false;
+    for (const PassRange &r : ranges)
+        if (r.g_end - r.g_begin == 1 && g[r.g_begin].op == QG_SWAP &&
+            std::min(g[r.g_begin].q0, g[r.g_begin].q1) >= line_bits)
+            special = true;
+    // Adjoint sweeps number their gradient rows across the whole program: one build.
+    if (cfg.reverse || (!special && (cfg.dense_min_gates >= (1 << 30) || cfg.n < 8)))
+        return build_program(g, ranges, cfg);
     Program prog;
     prog.pass_of_gate.assign(g.size(), -1);
     for (size_t p = 0; p < ranges.size(); ++p) {
         const PassRange &r = ranges[p];
-        const uint64_t blk = r.g_end - r.g_begin >= cfg.dense_min_gates
+        const Gate &g1 = g[r.g_begin];
+        if (!cfg.reverse && r.g_end - r.g_begin == 1 && g1.op == QG_SWAP && std::min(g1.q0, g1.q1) >= line_bits) {
+            // standalone SWAP: move only the half of the state whose two bits differ
+            PassDesc pd{};
+            pd.flags = PASS_SWAP2;
+            pd.run_start[0] = g1.q0;
+            pd.run_start[1] = g1.q1;
+            pd.n_tiles = 1ull << (cfg.n - 2);
+            prog.passes.push_back(pd);
+            prog.pass_of_gate[r.g_begin] = (int)p;
+            continue;
+        }
+        const uint64_t blk = (!cfg.reverse && cfg.n >= 8 && r.g_end - r.g_begin >= cfg.dense_min_gates)
                                  ? dense_block_qubits(g, r.g_begin, r.g_end, cfg.n) : 0;
         if (blk) {
             append_dense(&prog, g, r.g_begin, r.g_end, blk, cfg);
@@ -666,7 +700,7 @@ void append_program(Program *dst, const Program &src) {
     const int d0 = (int)dst->dense.size();
     const int64_t u0 = (int64_t)dst->dense_ut.size();
     for (PassDesc pd : src.passes) {
-        pd.phase_begin += (pd.flags & PASS_DENSE) ? d0 : ph0;
+        if (!(pd.flags & PASS_SWAP2)) pd.phase_begin += (pd.flags & PASS_DENSE) ? d0 : ph0;
         dst->passes.push_back(pd);
     }
     for (DenseDesc d : src.dense) {

@@ -28,6 +28,7 @@ struct PlanConfig {
     int fusion = QG_FUSE_GREEDY;
     bool reverse = false; // adjoint sweep: reversed gates, daggered, with gradient ops
     int flags = 0;        // PASS_* bits for every pass
+    int nt_mode = 1;      // 0 off, 1 only for line-aligned layouts, 2 always
     int swz_bits = 0;     // tile-order swizzle of the block index
     int max_gates_per_pass = 4096;
     int dense_min_gates = 1 << 30;  // a pass on <= 6 qubits with this many gates runs as a dense block
@@ -41,7 +42,7 @@ struct Tuning {
     int low_bits[2] = {7, 8};
     int max_high[2] = {5, 5};
     int nt = 1;
-    int swz_bits = 0;
+    int swz_bits = 4;
     int dense_min_gates = 1 << 30;
 };
 Tuning &tuning();
