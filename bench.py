@@ -169,6 +169,9 @@ def main():
     torch.cuda.set_device(0)
     n = args.n
     amp_bytes = 16 if args.dtype == "c128" else 8
+    from paper_2504_03967_amd import autotune
+    table, source = autotune.tuned(n, args.dtype)
+    log(f"autotuned tile shapes ({source}): {table}")
     prep, full, parts = W.sweep(n)
     st = qg.State(n, args.dtype)
     st.apply(prep, qg.FUSE_NONE)
@@ -222,32 +225,36 @@ def main():
     for name, e0, e1 in events:
         per.setdefault(name, []).append(e0.elapsed_time(e1) * 1e-3)
     pass_bytes = 2 * (1 << n) * amp_bytes
+    line_bits = 3 if args.dtype == "c128" else 4   # amplitudes per 128-byte line = 2^line_bits
+
+    def algo_frac(name):
+        """Algorithmic bytes of a part as a fraction of a full pass: the 128-byte lines that
+        hold an amplitude the gate changes, read and written once."""
+        if not name.startswith(("cx", "cp", "swap")):
+            return 1.0
+        a, b = (int(v) for v in name.split("_")[1:])
+        if name.startswith("cx"):
+            return 0.5 if a >= line_bits else 1.0
+        if name.startswith("cp"):
+            return 0.5 ** ((a >= line_bits) + (b >= line_bits))
+        return 0.5 if min(a, b) >= line_bits else 1.0
+
     u3 = np.array([np.mean(per[f"u3_t{t}"]) for t in range(n)])
     u3_gbs = pass_bytes / u3 / 1e9
-    achieved = pass_bytes / float(np.mean(u3)) / 1e9
-
-    def part_gbs(name, frac):
-        return round(frac * pass_bytes / float(np.mean(per[name])) / 1e9, 1)
-
     sweep = {"u3_GBps_min": round(float(u3_gbs.min()), 1),
              "u3_GBps_geomean": round(float(np.exp(np.mean(np.log(u3_gbs)))), 1),
              "u3_GBps_max": round(float(u3_gbs.max()), 1)}
-    # Bytes each part's pass moves: a single-gate tile holds the target and the
-    # lowest 11 other qubits (12 tile qubits); controls and diagonal qubits outside
-    # the tile restrict the pass to the tiles where their bits are 1.
-    tile_bits = 12 if args.dtype == "c128" else 13
     for name, _ in parts:
-        if name.startswith(("cx", "cp", "swap")):
-            a, b = (int(v) for v in name.split("_")[1:])
-            if name.startswith("cx"):
-                frac = 0.5 if a >= tile_bits - 1 else 1.0
-            elif name.startswith("cp"):
-                frac = 0.5 ** ((a >= tile_bits) + (b >= tile_bits))
-            else:
-                frac = 1.0
-            sweep[name + "_GBps"] = part_gbs(name, frac)
-        elif name.startswith("fused"):
-            sweep[name + "_GBps"] = part_gbs(name, 1.0)
+        if not name.startswith("u3"):
+            sweep[name + "_GBps"] = round(algo_frac(name) * pass_bytes / float(np.mean(per[name])) / 1e9, 1)
+    # Dominant kernel: the tile pass (every part except the standalone SWAPs of two qubits
+    # above the line bits, which run the permutation kernel).
+    tile_parts = [nm for nm, _ in parts
+                  if not (nm.startswith("swap") and algo_frac(nm) == 0.5)]
+    tile_bytes = sum(algo_frac(nm) * pass_bytes for nm in tile_parts)
+    tile_time = sum(float(np.mean(per[nm])) for nm in tile_parts)
+    achieved = tile_bytes / tile_time / 1e9
+    bytes_per_launch = tile_bytes / len(tile_parts)
     if args.parts_json:
         with open(args.parts_json, "w") as f:
             json.dump({k: float(np.mean(v)) for k, v in per.items()}, f, indent=1)
@@ -301,11 +308,15 @@ def main():
         "config": {"workload": f"gate sweep, {n} qubits {args.dtype}: U3 x{n} targets, CX/CP/SWAP x5 pairs, "
                                f"fused U3 groups k=2..6, then probs(1024), 10^4 shots, {n - 1} ZZ expvals",
                    "n_qubits": n, "gates_per_step": gates_per_step, "state_GiB": (1 << n) * amp_bytes / 2 ** 30},
-        "hbm_frac": achieved / HBM_PEAK_GBS,
+        "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_tile_inl (single-U3 pass)", "bytes_per_launch": pass_bytes},
+                     "kernel": "k_tile_inl (tile pass)", "launches_per_step": len(tile_parts),
+                     "algorithmic_bytes_per_launch": round(bytes_per_launch),
+                     "avg_launch_ms": round(tile_time / len(tile_parts) * 1e3, 4)},
         "sweep": sweep,
+        "autotune": {"source": source, "classes": "target <3 | <12 | <20 | >=20 | diagonal",
+                     "tile_reg_swz": table},
         "cpu_baseline": cpu,
     }
     out.update(extras)

@@ -2,6 +2,7 @@
 // the launch sequences of each entry point (declared and documented in qg.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -287,6 +288,7 @@ PlanConfig batch_config(int n, bool c64) {
     cfg.flags = 0;       // states are re-read by the same workgroup: keep them cacheable
     cfg.swz_bits = 0;
     cfg.max_gates_per_pass = n <= cfg.tile_bits ? (1 << 30) : 4096;
+    cfg.use_classes = false;  // the persistent kernel is built for one register width
     clamp_config(&cfg);
     return cfg;
 }
@@ -1247,6 +1249,84 @@ qg_status qg_set_cost_model(qg_mlp *M) {
     if (M && M->F != kPlanFeatures)
         return fail(QG_EINVAL, "cost model takes %d inputs, pass features are %d", M->F, kPlanFeatures);
     g_cost_model = M;
+    return QG_OK;
+}
+
+
+qg_status qg_autotune(qg_state *s, int reps, int32_t *table) {
+    if (!s) return fail(QG_EINVAL, "state is NULL");
+    if (reps < 1 || reps > 100) return fail(QG_EINVAL, "reps must be in [1, 100]");
+    const bool c64 = s->c64();
+    const int d = c64 ? 1 : 0;
+    const int n = s->n;
+    struct Cand {
+        int tile, reg, swz;
+    };
+    static const Cand c128[] = {{10, 2, 0}, {10, 2, 4}, {11, 3, 0}, {11, 3, 4}, {12, 4, 0}, {12, 4, 4}, {13, 4, 0}, {13, 4, 4}};
+    static const Cand cf64[] = {{10, 2, 0}, {11, 3, 0}, {11, 3, 4}, {12, 4, 0}, {12, 4, 4}, {12, 5, 4}, {13, 5, 0}, {13, 5, 4}};
+    const Cand *cand = c64 ? cf64 : c128;
+    const int n_cand = 8;
+    const int reps_target[kPassClasses] = {0, 8, 14, n - 1, n - 1};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0), "event");
+    HIP_TRY(hipEventCreate(&e1), "event");
+    Tuning &tu = tuning();
+    qg_status result = QG_OK;
+    for (int cls = 0; cls < kPassClasses && result == QG_OK; ++cls) {
+        const int t = reps_target[cls];
+        if (t >= n || pass_class(cls == 4 ? 0 : (1ull << t), c64) != cls) continue;
+        Gate g{};
+        g.op = cls == 4 ? QG_RZ : QG_U3;
+        g.q0 = -1;
+        g.q1 = t;
+        g.p[0] = 0.7;
+        g.p[1] = 0.3;
+        g.p[2] = 0.1;
+        g.pidx = -1;
+        std::vector<Gate> gl{g};
+        double best = 1e300;
+        Cand keep{tu.cls_tile[d][cls], tu.cls_reg[d][cls], tu.cls_swz[d][cls]};
+        for (int k = 0; k < n_cand && result == QG_OK; ++k) {
+            if (cand[k].tile > n) continue;
+            tu.cls_tile[d][cls] = cand[k].tile;
+            tu.cls_reg[d][cls] = cand[k].reg;
+            tu.cls_swz[d][cls] = cand[k].swz;
+            PlanConfig cfg = plan_config(n, c64, QG_FUSE_NONE);
+            Program prog = build_plan(gl, cfg);
+            std::vector<float> ms;
+            for (int r = 0; r <= reps && result == QG_OK; ++r) {
+                hipError_t e = hipEventRecord(e0, s->cx.stream);
+                if (e == hipSuccess) result = run_program(s->cx, c64, prog, s->buf, nullptr, nullptr);
+                if (result != QG_OK) break;
+                e = hipEventRecord(e1, s->cx.stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float v = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&v, e0, e1);
+                if (e != hipSuccess) result = hip_fail(e, "autotune timing");
+                if (r > 0) ms.push_back(v);  // first run warms up
+            }
+            if (result != QG_OK) break;
+            std::sort(ms.begin(), ms.end());
+            const double med = ms[ms.size() / 2];
+            if (med < best) {
+                best = med;
+                keep = cand[k];
+            }
+        }
+        tu.cls_tile[d][cls] = keep.tile;
+        tu.cls_reg[d][cls] = keep.reg;
+        tu.cls_swz[d][cls] = keep.swz;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != QG_OK) return result;
+    HIP_TRY(launch_zero_state(c64, s->buf, s->dim(), s->cx.stream), "state init");
+    if (table)
+        for (int cls = 0; cls < kPassClasses; ++cls) {
+            table[3 * cls] = tu.cls_tile[d][cls];
+            table[3 * cls + 1] = tu.cls_reg[d][cls];
+            table[3 * cls + 2] = tu.cls_swz[d][cls];
+        }
     return QG_OK;
 }
 

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 namespace qg {
@@ -138,20 +139,64 @@ struct Knob {
 };
 const Knob kKnobs[] = {
     {"tile_bits_c128", [](Tuning &t) { return &t.tile_bits[0]; }, 2, 13},
-    {"tile_bits_c64", [](Tuning &t) { return &t.tile_bits[1]; }, 2, 14},
+    {"tile_bits_c64", [](Tuning &t) { return &t.tile_bits[1]; }, 2, 13},
     {"reg_bits_c128", [](Tuning &t) { return &t.reg_bits[0]; }, 1, 4},
     {"reg_bits_c64", [](Tuning &t) { return &t.reg_bits[1]; }, 1, 5},
     {"low_bits_c128", [](Tuning &t) { return &t.low_bits[0]; }, 0, 13},
-    {"low_bits_c64", [](Tuning &t) { return &t.low_bits[1]; }, 0, 14},
+    {"low_bits_c64", [](Tuning &t) { return &t.low_bits[1]; }, 0, 13},
     {"max_high_c128", [](Tuning &t) { return &t.max_high[0]; }, 1, 13},
-    {"max_high_c64", [](Tuning &t) { return &t.max_high[1]; }, 1, 14},
+    {"max_high_c64", [](Tuning &t) { return &t.max_high[1]; }, 1, 13},
     {"nt", [](Tuning &t) { return &t.nt; }, 0, 2},
     {"swz_bits", [](Tuning &t) { return &t.swz_bits; }, 0, 16},
     {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 1, 1 << 30},
 };
 }  // namespace
 
+int pass_class(uint64_t required, bool c64) {
+    if (!required) return 4;
+    const int top = 63 - __builtin_clzll(required);
+    if (top < (c64 ? 4 : 3)) return 0;
+    if (top < 12) return 1;
+    if (top < 20) return 2;
+    return 3;
+}
+
+namespace {
+// "cls<k>_<tile|reg|swz>_<c128|c64>"
+int *class_knob(const char *key, int *lo, int *hi) {
+    int k = -1;
+    char what[8] = {0}, dt[8] = {0};
+    if (std::sscanf(key, "cls%d_%7[a-z]_%7[a-z0-9]", &k, what, dt) != 3) return nullptr;
+    if (k < 0 || k >= kPassClasses) return nullptr;
+    int d = std::strcmp(dt, "c128") == 0 ? 0 : std::strcmp(dt, "c64") == 0 ? 1 : -1;
+    if (d < 0) return nullptr;
+    Tuning &t = tuning();
+    if (std::strcmp(what, "tile") == 0) {
+        *lo = 4;
+        *hi = 13;  // 8 thread bits + at most 5 register bits
+        return &t.cls_tile[d][k];
+    }
+    if (std::strcmp(what, "reg") == 0) {
+        *lo = 1;
+        *hi = d ? 5 : 4;
+        return &t.cls_reg[d][k];
+    }
+    if (std::strcmp(what, "swz") == 0) {
+        *lo = 0;
+        *hi = 16;
+        return &t.cls_swz[d][k];
+    }
+    return nullptr;
+}
+}  // namespace
+
 int set_tuning(const char *key, int64_t value) {
+    int lo, hi;
+    if (int *f = class_knob(key, &lo, &hi)) {
+        if (value < lo || value > hi) return -1;
+        *f = (int)value;
+        return 0;
+    }
     for (const Knob &k : kKnobs) {
         if (std::strcmp(k.name, key) == 0) {
             if (value < k.lo || value > k.hi) return -1;
@@ -163,6 +208,11 @@ int set_tuning(const char *key, int64_t value) {
 }
 
 int get_tuning(const char *key, int64_t *value) {
+    int lo, hi;
+    if (int *f = class_knob(key, &lo, &hi)) {
+        *value = *f;
+        return 0;
+    }
     for (const Knob &k : kKnobs) {
         if (std::strcmp(k.name, key) == 0) {
             *value = *k.field(tuning());
@@ -406,8 +456,20 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
             }
             gate_items(g, cfg.reverse, row, &items);
         }
+        // ---- tile shape: single-gate passes take the tuned shape of their class
+        const Tuning &tu = tuning();
+        const int dcls = cfg.c64 ? 1 : 0;
+        const int cls = pass_class(req, cfg.c64);
+        int tile_bits = cfg.tile_bits, reg_bits = cfg.reg_bits, swz_bits = cfg.swz_bits;
+        if (cfg.use_classes && !cfg.reverse) {
+            if (r.g_end - r.g_begin == 1) {
+                tile_bits = tu.cls_tile[dcls][cls];
+                reg_bits = tu.cls_reg[dcls][cls];
+            }
+            swz_bits = tu.cls_swz[dcls][cls];
+        }
         // ---- tile: required qubits, then the lowest remaining ones
-        const int b = std::min(n, cfg.tile_bits);
+        const int b = std::min(n, std::max(tile_bits, popcount64(req)));
         uint64_t tile = req;
         for (int q = 0; q < n && popcount64(tile) < b; ++q) tile |= 1ull << q;
         int tile_q[kMaxTileBits];
@@ -416,7 +478,7 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
         int nb = 0;
         for (int q = 0; q < n; ++q)
             if (tile >> q & 1) { pos_of[q] = nb; tile_q[nb++] = q; }
-        int rb = std::min(cfg.reg_bits, b);
+        int rb = std::min(reg_bits, b);
         if (b - rb > kMaxThreadBits) rb = b - kMaxThreadBits;
         const int tb = b - rb;
 
@@ -452,7 +514,7 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
             free_bits++;
         }
         pd.n_tiles = 1ull << free_bits;
-        pd.swz_bits = std::min(cfg.swz_bits, free_bits / 2);
+        pd.swz_bits = std::min(swz_bits, free_bits / 2);
         pd.phase_begin = (int)prog.phases.size();
 
         // ---- phases: register positions must hold every mixing op's target

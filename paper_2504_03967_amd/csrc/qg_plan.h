@@ -32,7 +32,14 @@ struct PlanConfig {
     int swz_bits = 0;     // tile-order swizzle of the block index
     int max_gates_per_pass = 4096;
     int dense_min_gates = 1 << 30;  // a pass on <= 6 qubits with this many gates runs as a dense block
+    bool use_classes = true;        // single-gate passes take their tile shape from the class table
 };
+
+// Pass classes for tuning: by the highest qubit a pass needs in registers.
+// 0: below the cache-line bits, 1: below 12, 2: below 20, 3: 20 and above,
+// 4: no such qubit (diagonal-only pass).
+constexpr int kPassClasses = 5;
+int pass_class(uint64_t required, bool c64);
 
 // Process-wide tuning of the planner (defaults measured on MI355X; set by
 // qg_set_tuning or the autotuner).
@@ -44,6 +51,11 @@ struct Tuning {
     int nt = 1;
     int swz_bits = 4;
     int dense_min_gates = 1 << 30;
+    // Per pass class (see pass_class): tile bits, register bits and swizzle of
+    // single-gate passes, and the swizzle of fused passes.  [dtype][class]
+    int cls_tile[2][kPassClasses] = {{12, 12, 12, 10, 12}, {13, 13, 13, 11, 13}};
+    int cls_reg[2][kPassClasses] = {{4, 4, 4, 2, 4}, {5, 5, 5, 3, 5}};
+    int cls_swz[2][kPassClasses] = {{4, 4, 4, 0, 4}, {4, 4, 4, 0, 4}};
 };
 Tuning &tuning();
 // Returns 0 on success, -1 for an unknown key or out-of-range value.

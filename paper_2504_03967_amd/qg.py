@@ -28,6 +28,7 @@ EXPORTS = (
     "qg_batch_create", "qg_batch_set_params", "qg_batch_launch", "qg_batch_free",
     "qg_mlp_create", "qg_mlp_n_params", "qg_mlp_set_params", "qg_mlp_get_params", "qg_mlp_forward",
     "qg_mlp_grad", "qg_mlp_adam_step", "qg_mlp_train", "qg_mlp_free", "qg_pass_features", "qg_set_cost_model",
+    "qg_autotune",
 )
 PASS_FEATURES = 24
 PASS_CONFIGS = 5
@@ -80,6 +81,7 @@ def _load() -> ctypes.CDLL:
         "qg_mlp_free": [P],
         "qg_pass_features": [P, ctypes.c_int, ctypes.c_int, P, P],
         "qg_set_cost_model": [P],
+        "qg_autotune": [P, ctypes.c_int, P],
         "qg_set_tuning": [ctypes.c_char_p, I64],
         "qg_get_tuning": [ctypes.c_char_p, P],
     }
@@ -170,6 +172,12 @@ class State:
             self.close()
         except Exception:
             pass
+
+    def autotune(self, reps: int = 3) -> np.ndarray:
+        """Runs the library's autotuner on this state; returns the (tile, reg, swz) table [5, 3]."""
+        t = np.zeros((5, 3), np.int32)
+        _check(lib.qg_autotune(self.handle, int(reps), t.ctypes.data))
+        return t
 
     def set_stream(self, stream: Optional[torch.cuda.Stream]) -> None:
         self._stream = stream
