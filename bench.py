@@ -28,6 +28,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the tile pass measured with rocprofv3 FETCH_SIZE / WRITE_SIZE on this
+# benchmark (profiles/tile_pass_sweep30_c128.md), valid only for the kernel and planner
+# sources it was taken with (sha256 prefix of KERNEL_SOURCES); otherwise null.
+KERNEL_SOURCES = ("paper_2504_03967_amd/csrc/qg_tile_dev.h", "paper_2504_03967_amd/csrc/qg_tile.hip",
+                  "paper_2504_03967_amd/csrc/qg_plan.cpp", "paper_2504_03967_amd/csrc/qg_internal.h",
+                  "paper_2504_03967_amd/csrc/qg_api.cpp")
+MEASURED_TRAFFIC = {"sources": "", "traffic_over_algorithmic": None}
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -53,6 +70,22 @@ def timed(fn, sync):
     r = fn()
     sync()
     return time.perf_counter() - t0, r
+
+
+def config3_timing(qg, W, torch):
+    """The paper-shaped large circuit: 100 random U3 + CX layers and a QFT on 31 qubits
+    (complex128, 32 GiB state), greedy (commutation-aware) fusion."""
+    circ = W.config3(31)
+    st = qg.State(31, "c128")
+    _, npass = qg.plan_passes(circ, "c128", qg.FUSE_GREEDY)
+    st.apply(circ, qg.FUSE_GREEDY)  # warm-up (plans, code)
+    st.reset()
+    t, _ = timed(lambda: st.apply(circ, qg.FUSE_GREEDY), torch.cuda.synchronize)
+    st.close()
+    torch.cuda.empty_cache()
+    return {"workload": "31 qubits c128: 100 layers (U3 on every qubit, 15 low/high CX) + QFT(31), 5111 gates",
+            "passes": npass, "t_s": round(t, 3), "amp_updates_per_s": circ.n_gates * (1 << 31) / t,
+            "full_pass_equivalent_GBps": round(npass * 2 * (1 << 31) * 16 / t / 1e9, 1)}
 
 
 def adjoint_speedup(qg, W, torch):
@@ -282,8 +315,14 @@ def main():
                "sample": f"first {sample.n_gates} gates of the {n}-qubit sweep on a 2^{n} complex128 state "
                          f"(one FP64 pass per gate), {dt:.1f} s"}
 
+    traffic = None
+    if MEASURED_TRAFFIC["traffic_over_algorithmic"] and MEASURED_TRAFFIC["sources"] == kernel_sources_hash():
+        traffic = round(MEASURED_TRAFFIC["traffic_over_algorithmic"] * bytes_per_launch)
+
     extras = {}
     if not args.no_extras:
+        log("config 3 (31 qubits c128, 5111 gates) timing")
+        extras["config3"] = config3_timing(qg, W, torch)
         log("adjoint vs finite differences (config 5)")
         extras["adjoint"] = adjoint_speedup(qg, W, torch)
         log(f"adjoint speedup {extras['adjoint']['speedup']}x; batched vs plain loop (config 4)")
@@ -310,7 +349,7 @@ def main():
                    "n_qubits": n, "gates_per_step": gates_per_step, "state_GiB": (1 << n) * amp_bytes / 2 ** 30},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_tile_inl (tile pass)", "launches_per_step": len(tile_parts),
                      "algorithmic_bytes_per_launch": round(bytes_per_launch),
                      "avg_launch_ms": round(tile_time / len(tile_parts) * 1e3, 4)},
