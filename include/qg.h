@@ -251,6 +251,9 @@ qg_status qg_set_cost_model(qg_mlp *m);
  *   nt                               non-temporal state loads/stores: 0 off, 1 when every
  *                                    wavefront access covers whole cache lines, 2 always
  *   swz_bits                         tile-order swizzle of the launch
+ *   xcd                              1: each of the 8 XCDs streams a contiguous eighth
+ *                                    of a pass's tiles (blocks are dealt to XCDs in
+ *                                    turn); 0: block b takes tile b
  * Errors: QG_EINVAL for an unknown key or a value out of range.  Not
  * thread-safe against concurrent planning. */
 qg_status qg_set_tuning(const char *key, int64_t value);

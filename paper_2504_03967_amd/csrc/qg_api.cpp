@@ -225,7 +225,7 @@ qg_status run_program(Ctx &cx, bool c64, const Program &prog, void *psi, void *l
         const PassDesc &pd = prog.passes[p];
         if (pd.flags & PASS_SWAP2) {
             const int n = __builtin_ctzll(pd.n_tiles) + 2;
-            HIP_TRY(launch_swap2(c64, psi, n, pd.run_start[0], pd.run_start[1], cx.stream), "swap kernel launch");
+            HIP_TRY(launch_swap2(c64, psi, n, pd.run_start[0], pd.run_start[1], (pd.flags & PASS_XCD) != 0, cx.stream), "swap kernel launch");
             continue;
         }
         if (pd.flags & PASS_DENSE) {

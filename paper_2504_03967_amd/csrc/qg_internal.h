@@ -68,6 +68,7 @@ enum PassFlags : int32_t {
     PASS_NT = 1,     // non-temporal loads and stores of the state (streaming, no reuse)
     PASS_DENSE = 2,  // the pass is a dense block: phase_begin indexes the program's DenseDesc list
     PASS_SWAP2 = 4,  // the pass is a standalone SWAP of qubits run_start[0] and run_start[1]
+    PASS_XCD = 8,    // tile order: block b takes tile (b mod 8) * n_tiles / 8 + b / 8
 };
 
 // A dense k-qubit block (k in 4..6): tiles are the block qubits blk_q plus the l

@@ -148,6 +148,7 @@ const Knob kKnobs[] = {
     {"max_high_c64", [](Tuning &t) { return &t.max_high[1]; }, 1, 13},
     {"nt", [](Tuning &t) { return &t.nt; }, 0, 2},
     {"swz_bits", [](Tuning &t) { return &t.swz_bits; }, 0, 16},
+    {"xcd", [](Tuning &t) { return &t.xcd; }, 0, 1},
     {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 1, 1 << 30},
 };
 }  // namespace
@@ -515,6 +516,7 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
         }
         pd.n_tiles = 1ull << free_bits;
         pd.swz_bits = std::min(swz_bits, free_bits / 2);
+        if (tu.xcd && free_bits >= 3) pd.flags |= PASS_XCD;
         pd.phase_begin = (int)prog.phases.size();
 
         // ---- phases: register positions must hold every mixing op's target
@@ -736,7 +738,7 @@ Program build_plan(const std::vector<Gate> &g0, const PlanConfig &cfg, std::vect
         if (!cfg.reverse && r.g_end - r.g_begin == 1 && g1.op == QG_SWAP && std::min(g1.q0, g1.q1) >= line_bits) {
             // standalone SWAP: move only the half of the state whose two bits differ
             PassDesc pd{};
-            pd.flags = PASS_SWAP2;
+            pd.flags = PASS_SWAP2 | (tuning().xcd ? PASS_XCD : 0);
             pd.run_start[0] = g1.q0;
             pd.run_start[1] = g1.q1;
             pd.n_tiles = 1ull << (cfg.n - 2);

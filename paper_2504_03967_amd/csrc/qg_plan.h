@@ -50,6 +50,7 @@ struct Tuning {
     int max_high[2] = {5, 5};
     int nt = 1;
     int swz_bits = 4;
+    int xcd = 1;
     int dense_min_gates = 1 << 30;
     // Per pass class (see pass_class): tile bits, register bits and swizzle of
     // single-gate passes, and the swizzle of fused passes.  [dtype][class]

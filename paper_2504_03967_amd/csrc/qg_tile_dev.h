@@ -165,6 +165,12 @@ __device__ __forceinline__ double grad_xy(const C (&a)[NS][NR], bool isy) {
 // Global index bits of tile w: deposit w into the free runs (after the optional swizzle).
 __device__ __forceinline__ uint64_t tile_gbase(const PassDesc &P, uint64_t w) {
     uint64_t gbase = P.fixed_val;
+    if (P.flags & PASS_XCD) {
+        // Blocks are dealt to the 8 XCDs in turn: give each XCD a contiguous
+        // eighth of the tiles.
+        const int lt = 63 - __builtin_clzll(P.n_tiles);
+        w = ((w & 7) << (lt - 3)) | (w >> 3);
+    }
     if (P.swz_bits > 0) {
         // Neighbouring blocks take tiles whose addresses differ in higher bits.
         const uint64_t m = (1ull << P.swz_bits) - 1;

@@ -229,3 +229,31 @@ def test_validation_errors_leave_state_untouched(qg):
     with pytest.raises(qg.QGError):
         st.apply(nan)
     assert np.array_equal(host(st), before)
+
+
+def test_tile_order_settings_are_bitwise_identical(qg):
+    """The tile order of a launch (XCD-contiguous ranges, XOR swizzle) only changes which
+    workgroup streams which tile: the state must come out bit for bit the same, and match
+    the oracle.  The circuit has fused, single-gate, controlled and standalone-SWAP passes."""
+    n = 17
+    circ = W.concat(W.random_circuit(n, 120, seed=41),
+                    W.CircuitBuilder(n).g2(W.SWAP, 5, 14).g2(W.SWAP, 16, 9).g2(W.CX, 15, 3).build())
+    ref = oracle.simulate(circ)
+    keys = ("xcd", "swz_bits") + tuple(f"cls{k}_swz_c128" for k in range(5))
+    saved = {k: qg.get_tuning(k) for k in keys}
+    states = []
+    try:
+        for xcd in (0, 1):
+            for swz in (0, 3):
+                qg.set_tuning("xcd", xcd)
+                for k in keys[1:]:
+                    qg.set_tuning(k, swz)
+                st = run(qg, circ)
+                states.append(host(st))
+                st.close()
+    finally:
+        for k, v in saved.items():
+            qg.set_tuning(k, v)
+    assert np.max(np.abs(states[0] - ref)) < TOL["c128"]
+    for s in states[1:]:
+        assert np.array_equal(s, states[0])
