@@ -254,6 +254,11 @@ qg_status qg_set_cost_model(qg_mlp *m);
  *   xcd                              1: each of the 8 XCDs streams a contiguous eighth
  *                                    of a pass's tiles (blocks are dealt to XCDs in
  *                                    turn); 0: block b takes tile b
+ *   pipe                             forward passes on persistent blocks that load
+ *                                    their next tile while computing the current one:
+ *                                    0 never, 1 passes with several register layouts
+ *                                    or at least pipe_min_ops ops, 2 always
+ *   pipe_min_ops                     see pipe
  * Errors: QG_EINVAL for an unknown key or a value out of range.  Not
  * thread-safe against concurrent planning. */
 qg_status qg_set_tuning(const char *key, int64_t value);

@@ -22,7 +22,7 @@ constexpr int kMaxRuns = 20;
 
 enum OpKind : int32_t {
     OP_MAT = 0,    // dense 2x2 on register slot a: m = {m00, m01, m10, m11} (re, im)
-    OP_CMAT = 1,   // 2x2 on register slot a where the bit of qubit-ref c is 1
+    OP_CX = 1,     // exchange the pair on register slot a where the bit of qubit-ref c is 1
     OP_DIAG1 = 2,  // amplitude *= (bit of ref a ? {m[2],m[3]} : {m[0],m[1]})
     OP_DIAG2 = 3,  // amplitude *= {m[0], m[1]} where bits of refs a and c are both 1
     OP_GRADX = 4,  // adjoint partial: Im<lam|X_a|psi>, a = register slot, into grad row g
@@ -69,6 +69,7 @@ enum PassFlags : int32_t {
     PASS_DENSE = 2,  // the pass is a dense block: phase_begin indexes the program's DenseDesc list
     PASS_SWAP2 = 4,  // the pass is a standalone SWAP of qubits run_start[0] and run_start[1]
     PASS_XCD = 8,    // tile order: block b takes tile (b mod 8) * n_tiles / 8 + b / 8
+    PASS_PIPE = 16,  // persistent blocks that load their next tile while computing the current one
 };
 
 // A dense k-qubit block (k in 4..6): tiles are the block qubits blk_q plus the l

@@ -79,11 +79,9 @@ void gate_items(const Gate &g, bool dagger, int grad_row, std::vector<Item> *out
         out->push_back(it);
         return;
     case QG_CX:
-        it.kind = OP_CMAT;
+        it.kind = OP_CX;
         it.qc = g.q0;
         it.qa = g.q1;
-        put(it.m, 1, 1.0);
-        put(it.m, 2, 1.0);
         out->push_back(it);
         return;
     case QG_CZ:
@@ -100,12 +98,10 @@ void gate_items(const Gate &g, bool dagger, int grad_row, std::vector<Item> *out
         int seq[3][2] = {{a, b}, {b, a}, {a, b}};
         for (auto &s : seq) {
             Item x{};
-            x.kind = OP_CMAT;
+            x.kind = OP_CX;
             x.g = -1;
             x.qc = s[0];
             x.qa = s[1];
-            put(x.m, 1, 1.0);
-            put(x.m, 2, 1.0);
             out->push_back(x);
         }
         return;
@@ -116,7 +112,7 @@ void gate_items(const Gate &g, bool dagger, int grad_row, std::vector<Item> *out
 int needs_register(const Item &it) {
     switch (it.kind) {
     case OP_MAT:
-    case OP_CMAT:
+    case OP_CX:
     case OP_GRADX:
     case OP_GRADY:
         return it.qa;
@@ -149,6 +145,8 @@ const Knob kKnobs[] = {
     {"nt", [](Tuning &t) { return &t.nt; }, 0, 2},
     {"swz_bits", [](Tuning &t) { return &t.swz_bits; }, 0, 16},
     {"xcd", [](Tuning &t) { return &t.xcd; }, 0, 1},
+    {"pipe", [](Tuning &t) { return &t.pipe; }, 0, 2},
+    {"pipe_min_ops", [](Tuning &t) { return &t.pipe_min_ops; }, 1, 1 << 20},
     {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 1, 1 << 30},
 };
 }  // namespace
@@ -487,7 +485,7 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
         uint64_t fixed = items.empty() ? 0 : ~0ull;
         for (const Item &it : items) {
             uint64_t cond = 0;
-            if (it.kind == OP_CMAT && pos_of[it.qc] < 0) cond = 1ull << it.qc;
+            if (it.kind == OP_CX && pos_of[it.qc] < 0) cond = 1ull << it.qc;
             if (it.kind == OP_DIAG2 || it.kind == OP_GRADP11) {
                 if (pos_of[it.qa] < 0) cond |= 1ull << it.qa;
                 if (pos_of[it.qc] < 0) cond |= 1ull << it.qc;
@@ -563,7 +561,7 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
                 case OP_MAT: case OP_GRADX: case OP_GRADY:
                     op.a = slot;
                     break;
-                case OP_CMAT:
+                case OP_CX:
                     op.a = slot;
                     op.c = ref(it.qc);
                     break;
@@ -582,6 +580,9 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
             first = false;
         }
         pd.n_phase = (int)prog.phases.size() - pd.phase_begin;
+        const int n_ops = prog.phases.back().op_end - prog.phases[pd.phase_begin].op_begin;
+        if (!cfg.reverse && (tu.pipe == 2 || (tu.pipe == 1 && (pd.n_phase > 1 || n_ops >= tu.pipe_min_ops))))
+            pd.flags |= PASS_PIPE;
         // Non-temporal state accesses only pay when every wavefront load/store
         // covers whole 128-byte lines: the first and last layouts must keep the
         // line-offset tile positions (3 for complex128, 4 for complex64) on lanes.

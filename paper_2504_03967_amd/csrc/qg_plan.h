@@ -51,6 +51,8 @@ struct Tuning {
     int nt = 1;
     int swz_bits = 4;
     int xcd = 1;
+    int pipe = 0;          // persistent prefetching blocks: 0 never, 1 heavy passes, 2 always
+    int pipe_min_ops = 4;  // a pass is heavy with several phases or at least this many ops
     int dense_min_gates = 1 << 30;
     // Per pass class (see pass_class): tile bits, register bits and swizzle of
     // single-gate passes, and the swizzle of fused passes.  [dtype][class]

@@ -2,6 +2,9 @@
 // state through registers and applies the pass's ops (App. A: single-qubit
 // operators of eq. (tp), controlled operators of eq. (cx), the diagonal CR1 of
 // eq. (cr1)).  Every pass reads and writes each active amplitude once.
+#include <mutex>
+#include <vector>
+
 #include "qg_kernels.h"
 #include "qg_tile_dev.h"
 
@@ -27,6 +30,64 @@ __device__ __forceinline__ void tile_pass(const PassDesc &P, const PhaseDesc *__
     tile_store<R, RB, NS>(P, phases[P.n_phase - 1], gbase, st, a, tid);
 }
 
+// Persistent form (forward passes): each block walks a strided sequence of
+// tiles and issues the loads of its next tile before computing the current
+// one, so that memory traffic overlaps the arithmetic and the LDS exchanges.
+// With PASS_XCD the blocks of XCD x (x = block mod 8) cover the x-th eighth
+// of the tiles; the host launches a multiple of 8 blocks, at most n_tiles.
+template <typename R, int RB>
+__device__ __forceinline__ void tile_pass_pipe(const PassDesc &P, const PhaseDesc *__restrict__ phases,
+                                               const DevOp *__restrict__ ops, typename V2<R>::T *__restrict__ psi) {
+    using C = typename V2<R>::T;
+    constexpr int NR = 1 << RB;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    const int tid = threadIdx.x;
+    const uint64_t T = P.n_tiles, G = gridDim.x;
+    uint64_t w, step, end;
+    if (P.flags & PASS_XCD) {
+        const uint64_t span = T >> 3;
+        w = (blockIdx.x & 7) * span + (blockIdx.x >> 3);
+        step = G >> 3;
+        end = ((blockIdx.x & 7) + 1) * span;
+    } else {
+        w = blockIdx.x;
+        step = G;
+        end = T;
+    }
+    C *const st[2] = {psi, nullptr};
+    C a[1][NR], nx[1][NR];
+    const PhaseDesc &first = phases[0];
+    const PhaseDesc &last = phases[P.n_phase - 1];
+    tile_load<R, RB, 1>(P, first, tile_deposit(P, w), st, a, tid);
+    for (;;) {
+        const uint64_t wn = w + step;
+        const bool more = wn < end;
+        if (more) tile_load<R, RB, 1>(P, first, tile_deposit(P, wn), st, nx, tid);
+        const uint64_t gbase = tile_deposit(P, w);
+        tile_phases<R, RB, 1>(P, phases, ops, gbase, a, lds, nullptr, 0, w, tid, true);
+        tile_store<R, RB, 1>(P, last, gbase, st, a, tid);
+        if (!more) break;
+#pragma unroll
+        for (int e = 0; e < NR; ++e) a[0][e] = nx[0][e];
+        w = wn;
+    }
+}
+
+template <typename R, int RB>
+__global__ void __launch_bounds__(256)
+k_tile_pipe(const unsigned char *__restrict__ dev, uint32_t pass_off, uint32_t phase_off, uint32_t op_off,
+            int pass_idx, typename V2<R>::T *__restrict__ psi) {
+    const PassDesc &P = reinterpret_cast<const PassDesc *>(dev + pass_off)[pass_idx];
+    tile_pass_pipe<R, RB>(P, reinterpret_cast<const PhaseDesc *>(dev + phase_off) + P.phase_begin,
+                          reinterpret_cast<const DevOp *>(dev + op_off), psi);
+}
+
+template <typename R, int RB>
+__global__ void __launch_bounds__(256) k_tile_inl_pipe(const InlineProg prog, typename V2<R>::T *__restrict__ psi) {
+    tile_pass_pipe<R, RB>(prog.pass, prog.phases, prog.ops, psi);
+}
+
 template <typename R, int RB, int NS>
 __global__ void __launch_bounds__(256)
 k_tile(const unsigned char *__restrict__ dev, uint32_t pass_off, uint32_t phase_off, uint32_t op_off,
@@ -44,25 +105,71 @@ k_tile_inl(const InlineProg prog, typename V2<R>::T *__restrict__ psi, typename 
     tile_pass<R, RB, NS>(prog.pass, prog.phases, prog.ops, psi, lam, gpart, gstride);
 }
 
+// Resident blocks per CU of a kernel at a block size and dynamic LDS size,
+// times the CU count (cached per kernel, configuration and device).
+int resident_blocks(const void *fn, int threads, size_t lds) {
+    struct Key {
+        const void *fn;
+        int threads;
+        size_t lds;
+        int dev;
+        int blocks;
+    };
+    static std::mutex mu;
+    static std::vector<Key> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Key &k : cache)
+        if (k.fn == fn && k.threads == threads && k.lds == lds && k.dev == dev) return k.blocks;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    cache.push_back({fn, threads, lds, dev, per_cu * cus});
+    return per_cu * cus;
+}
+
 template <typename R, int RB, int NS>
 hipError_t launch_one(const PassDesc &hp, const InlineProg *inl, const void *dev, size_t pass_off,
                       size_t phase_off, size_t op_off, int pass_idx, void *psi, void *lam, double *gpart,
                       int64_t gstride, hipStream_t st) {
     using C = typename V2<R>::T;
     const size_t lds = hp.n_phase > 1 ? (size_t(1) << hp.b) * sizeof(C) : 0;
+    const bool pipe = NS == 1 && (hp.flags & PASS_PIPE);
     if (lds > 65536) {
         static bool done = false;
         if (!done) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<R, RB, NS>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            if (e == hipSuccess)
-                e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile_inl<R, RB, NS>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            hipError_t e = hipSuccess;
+            for (const void *fn : {reinterpret_cast<const void *>(&k_tile<R, RB, NS>),
+                                   reinterpret_cast<const void *>(&k_tile_inl<R, RB, NS>),
+                                   reinterpret_cast<const void *>(&k_tile_pipe<R, RB>),
+                                   reinterpret_cast<const void *>(&k_tile_inl_pipe<R, RB>)})
+                if (e == hipSuccess) e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             if (e != hipSuccess) return e;
             done = true;
         }
     }
-    dim3 grid((uint32_t)hp.n_tiles), block(1u << hp.tb);
+    dim3 block(1u << hp.tb);
+    if (pipe) {
+        const void *fn = inl ? reinterpret_cast<const void *>(&k_tile_inl_pipe<R, RB>)
+                             : reinterpret_cast<const void *>(&k_tile_pipe<R, RB>);
+        uint64_t g = (uint64_t)resident_blocks(fn, (int)block.x, lds);
+        if (g == 0) return hipErrorInvalidValue;
+        if (g > hp.n_tiles) g = hp.n_tiles;
+        // The XCD schedule needs a multiple of 8 blocks (n_tiles >= 8 under PASS_XCD).
+        if (hp.flags & PASS_XCD) g &= ~7ull;
+        if (g == 0) return hipErrorInvalidValue;
+        if (inl) {
+            hipLaunchKernelGGL((k_tile_inl_pipe<R, RB>), dim3((uint32_t)g), block, lds, st, *inl,
+                               static_cast<C *>(psi));
+        } else {
+            hipLaunchKernelGGL((k_tile_pipe<R, RB>), dim3((uint32_t)g), block, lds, st,
+                               static_cast<const unsigned char *>(dev), (uint32_t)pass_off, (uint32_t)phase_off,
+                               (uint32_t)op_off, pass_idx, static_cast<C *>(psi));
+        }
+        return hipGetLastError();
+    }
+    dim3 grid((uint32_t)hp.n_tiles);
     if (inl) {
         hipLaunchKernelGGL((k_tile_inl<R, RB, NS>), grid, block, lds, st, *inl, static_cast<C *>(psi),
                            static_cast<C *>(lam), gpart, gstride);

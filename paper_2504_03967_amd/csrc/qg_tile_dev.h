@@ -124,21 +124,23 @@ __device__ __forceinline__ void apply_mat(C (&a)[NS][NR], const R (&m)[8]) {
         }
 }
 
-template <int J, int NS, int NR, typename C, typename R>
-__device__ __forceinline__ void apply_cmat(C (&a)[NS][NR], const R (&m)[8], uint32_t tp, const uint32_t (&ep)[NR],
-                                           int cref) {
+// Controlled X: exchange the amplitudes of each pair on register slot J
+// where the control bit is 1.  cref >= 0 is the control's tile position;
+// otherwise the control lies outside the tile and fixed_on is its value there.
+template <int J, int NS, int NR, typename C>
+__device__ __forceinline__ void apply_cx(C (&a)[NS][NR], uint32_t tp, const uint32_t (&ep)[NR], int cref,
+                                         bool fixed_on) {
     constexpr int jb = 1 << J;
     const uint32_t cm = cref >= 0 ? (1u << cref) : 0u;
 #pragma unroll
     for (int e = 0; e < NR; ++e) {
         if (e & jb) continue;
-        const bool on = cm == 0u || ((tp | ep[e]) & cm) != 0u;
+        const bool on = cm == 0u ? fixed_on : ((tp | ep[e]) & cm) != 0u;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            C o0, o1;
-            mat2(m, a[s][e], a[s][e | jb], o0, o1);
-            a[s][e] = sel(on, o0, a[s][e]);
-            a[s][e | jb] = sel(on, o1, a[s][e | jb]);
+            const C x = a[s][e], y = a[s][e | jb];
+            a[s][e] = sel(on, y, x);
+            a[s][e | jb] = sel(on, x, y);
         }
     }
 }
@@ -162,15 +164,44 @@ __device__ __forceinline__ double grad_xy(const C (&a)[NS][NR], bool isy) {
 }
 
 
-// Global index bits of tile w: deposit w into the free runs (after the optional swizzle).
-__device__ __forceinline__ uint64_t tile_gbase(const PassDesc &P, uint64_t w) {
-    uint64_t gbase = P.fixed_val;
-    if (P.flags & PASS_XCD) {
-        // Blocks are dealt to the 8 XCDs in turn: give each XCD a contiguous
-        // eighth of the tiles.
-        const int lt = 63 - __builtin_clzll(P.n_tiles);
-        w = ((w & 7) << (lt - 3)) | (w >> 3);
+// Global index bits of logical tile w: deposit w into the free runs (after
+// the optional swizzle).
+// Calls the slot-J form of an op for the runtime slot `slot` < NR's bit count:
+// the last slot is the fall-through, so that no path leaves the registers
+// untouched (an untouched path makes the compiler copy the whole register
+// array around every op).
+template <int J, int RB, int NS, typename C, typename R>
+__device__ __forceinline__ void dispatch_mat(int slot, C (&a)[NS][1 << RB], const R (&m)[8]) {
+    if constexpr (J == RB - 1) {
+        apply_mat<J>(a, m);
+    } else {
+        if (slot == J) apply_mat<J>(a, m);
+        else dispatch_mat<J + 1, RB>(slot, a, m);
     }
+}
+
+template <int J, int RB, int NS, typename C>
+__device__ __forceinline__ void dispatch_cx(int slot, C (&a)[NS][1 << RB], uint32_t tp,
+                                            const uint32_t (&ep)[1 << RB], int cref, bool fixed_on) {
+    if constexpr (J == RB - 1) {
+        apply_cx<J>(a, tp, ep, cref, fixed_on);
+    } else {
+        if (slot == J) apply_cx<J>(a, tp, ep, cref, fixed_on);
+        else dispatch_cx<J + 1, RB>(slot, a, tp, ep, cref, fixed_on);
+    }
+}
+
+template <int J, int RB, int NS, typename C>
+__device__ __forceinline__ double dispatch_grad_xy(int slot, const C (&a)[NS][1 << RB], bool isy) {
+    if constexpr (J == RB - 1) {
+        return grad_xy<J>(a, isy);
+    } else {
+        return slot == J ? grad_xy<J>(a, isy) : dispatch_grad_xy<J + 1, RB>(slot, a, isy);
+    }
+}
+
+__device__ __forceinline__ uint64_t tile_deposit(const PassDesc &P, uint64_t w) {
+    uint64_t gbase = P.fixed_val;
     if (P.swz_bits > 0) {
         // Neighbouring blocks take tiles whose addresses differ in higher bits.
         const uint64_t m = (1ull << P.swz_bits) - 1;
@@ -182,6 +213,17 @@ __device__ __forceinline__ uint64_t tile_gbase(const PassDesc &P, uint64_t w) {
         w >>= len;
     }
     return gbase;
+}
+
+// Global index bits of the tile of block w (one tile per block).
+__device__ __forceinline__ uint64_t tile_gbase(const PassDesc &P, uint64_t w) {
+    if (P.flags & PASS_XCD) {
+        // Blocks are dealt to the 8 XCDs in turn: give each XCD a contiguous
+        // eighth of the tiles.
+        const int lt = 63 - __builtin_clzll(P.n_tiles);
+        w = ((w & 7) << (lt - 3)) | (w >> 3);
+    }
+    return tile_deposit(P, w);
 }
 
 __device__ __forceinline__ uint64_t thread_goff(const PhaseDesc &ph, int tb, int tid) {
@@ -338,19 +380,26 @@ __device__ __forceinline__ void tile_phases(const PassDesc &P, const PhaseDesc *
             if (kind == OP_MAT) {
                 switch (op.a) {
                 case 0: apply_mat<0>(a, m); break;
-                case 1: if constexpr (RB > 1) apply_mat<1>(a, m); break;
-                case 2: if constexpr (RB > 2) apply_mat<2>(a, m); break;
-                case 3: if constexpr (RB > 3) apply_mat<3>(a, m); break;
-                case 4: if constexpr (RB > 4) apply_mat<4>(a, m); break;
+                case 1: if constexpr (RB > 1) apply_mat<1>(a, m); else __builtin_unreachable(); break;
+                case 2: if constexpr (RB > 2) apply_mat<2>(a, m); else __builtin_unreachable(); break;
+                case 3: if constexpr (RB > 3) apply_mat<3>(a, m); else __builtin_unreachable(); break;
+                case 4: if constexpr (RB > 4) apply_mat<4>(a, m); else __builtin_unreachable(); break;
+                default: __builtin_unreachable();
                 }
-            } else if (kind == OP_CMAT) {
-                if (op.c < 0 && !((gbase >> (-1 - op.c)) & 1ull)) continue;
+            } else if (kind == OP_CX) {
+                // A control outside the tile is constant over the tile; when it
+                // is 0 every select keeps the input (no branch: a path that
+                // leaves the registers untouched costs a copy of all of them).
+                const bool fon = make_bit(op.c, gbase).fixed_one;
+                // Slots are < RB (checked by the planner); a path that leaves the
+                // registers untouched would make the compiler copy all of them.
                 switch (op.a) {
-                case 0: apply_cmat<0>(a, m, tp, ep, op.c); break;
-                case 1: if constexpr (RB > 1) apply_cmat<1>(a, m, tp, ep, op.c); break;
-                case 2: if constexpr (RB > 2) apply_cmat<2>(a, m, tp, ep, op.c); break;
-                case 3: if constexpr (RB > 3) apply_cmat<3>(a, m, tp, ep, op.c); break;
-                case 4: if constexpr (RB > 4) apply_cmat<4>(a, m, tp, ep, op.c); break;
+                case 0: apply_cx<0>(a, tp, ep, op.c, fon); break;
+                case 1: if constexpr (RB > 1) apply_cx<1>(a, tp, ep, op.c, fon); else __builtin_unreachable(); break;
+                case 2: if constexpr (RB > 2) apply_cx<2>(a, tp, ep, op.c, fon); else __builtin_unreachable(); break;
+                case 3: if constexpr (RB > 3) apply_cx<3>(a, tp, ep, op.c, fon); else __builtin_unreachable(); break;
+                case 4: if constexpr (RB > 4) apply_cx<4>(a, tp, ep, op.c, fon); else __builtin_unreachable(); break;
+                default: __builtin_unreachable();
                 }
             } else if (kind == OP_DIAG1) {
                 const Bit ba = make_bit(op.a, gbase);
@@ -369,8 +418,10 @@ __device__ __forceinline__ void tile_phases(const PassDesc &P, const PhaseDesc *
 #pragma unroll
                     for (int s = 0; s < NS; ++s) a[s][e] = sel(both, cmul(a[s][e], m[0], m[1]), a[s][e]);
                 }
+            } else if constexpr (NS == 1) {
+                // gradient ops only occur in adjoint programs
             } else {
-                if constexpr (NS == 2) {
+                {
                     double acc = 0.0;
                     if (kind == OP_GRADZ) {
                         const Bit ba = make_bit(op.a, gbase);
@@ -388,13 +439,7 @@ __device__ __forceinline__ void tile_phases(const PassDesc &P, const PhaseDesc *
                         }
                     } else {
                         const bool isy = kind == OP_GRADY;
-                        switch (op.a) {
-                        case 0: acc = grad_xy<0>(a, isy); break;
-                        case 1: if constexpr (RB > 1) acc = grad_xy<1>(a, isy); break;
-                        case 2: if constexpr (RB > 2) acc = grad_xy<2>(a, isy); break;
-                        case 3: if constexpr (RB > 3) acc = grad_xy<3>(a, isy); break;
-                        case 4: if constexpr (RB > 4) acc = grad_xy<4>(a, isy); break;
-                        }
+                        acc = dispatch_grad_xy<0, RB>(op.a, a, isy);
                     }
                     const int width = blockDim.x < 64 ? (int)blockDim.x : 64;
                     acc = wave_sum(acc, width);

@@ -232,28 +232,49 @@ def test_validation_errors_leave_state_untouched(qg):
 
 
 def test_tile_order_settings_are_bitwise_identical(qg):
-    """The tile order of a launch (XCD-contiguous ranges, XOR swizzle) only changes which
-    workgroup streams which tile: the state must come out bit for bit the same, and match
-    the oracle.  The circuit has fused, single-gate, controlled and standalone-SWAP passes."""
-    n = 17
-    circ = W.concat(W.random_circuit(n, 120, seed=41),
+    """The tile order of a launch (XCD-contiguous ranges, XOR swizzle, persistent blocks that
+    prefetch their next tile) only changes which workgroup streams which tile: the state must
+    come out bit for bit the same, and match the oracle.  The circuit has fused, single-gate,
+    controlled and standalone-SWAP passes."""
+    n = 22  # 1024 tiles: persistent blocks stream several tiles each
+    circ = W.concat(W.random_circuit(n, 80, seed=41),
                     W.CircuitBuilder(n).g2(W.SWAP, 5, 14).g2(W.SWAP, 16, 9).g2(W.CX, 15, 3).build())
     ref = oracle.simulate(circ)
-    keys = ("xcd", "swz_bits") + tuple(f"cls{k}_swz_c128" for k in range(5))
+    keys = ("xcd", "pipe", "swz_bits") + tuple(f"cls{k}_swz_c128" for k in range(5))
     saved = {k: qg.get_tuning(k) for k in keys}
     states = []
     try:
-        for xcd in (0, 1):
-            for swz in (0, 3):
-                qg.set_tuning("xcd", xcd)
-                for k in keys[1:]:
-                    qg.set_tuning(k, swz)
-                st = run(qg, circ)
-                states.append(host(st))
-                st.close()
+        for xcd, pipe, swz in ((0, 0, 0), (0, 0, 3), (1, 0, 0), (1, 0, 3), (0, 2, 0), (1, 2, 3), (1, 1, 0)):
+            qg.set_tuning("xcd", xcd)
+            qg.set_tuning("pipe", pipe)
+            for k in keys[2:]:
+                qg.set_tuning(k, swz)
+            st = run(qg, circ)
+            states.append(host(st))
+            st.close()
     finally:
         for k, v in saved.items():
             qg.set_tuning(k, v)
     assert np.max(np.abs(states[0] - ref)) < TOL["c128"]
     for s in states[1:]:
         assert np.array_equal(s, states[0])
+
+
+def test_persistent_prefetching_blocks_complex64(qg):
+    """complex64 passes on persistent blocks (several tiles per block, prefetch of the next
+    tile) give the same bits as one tile per block."""
+    n = 24
+    circ = W.random_circuit(n, 60, seed=43)
+    saved = qg.get_tuning("pipe")
+    out = []
+    try:
+        for pipe in (0, 2):
+            qg.set_tuning("pipe", pipe)
+            st = run(qg, circ, "c64")
+            torch.cuda.synchronize()
+            out.append(st.tensor.cpu().numpy())
+            st.close()
+    finally:
+        qg.set_tuning("pipe", saved)
+    assert np.array_equal(out[0], out[1])
+    assert abs(np.sum(np.abs(out[0].astype(np.complex128)) ** 2) - 1) < 1e-4
