@@ -28,7 +28,13 @@ enum OpKind : int32_t {
     OP_GRADX = 4,  // adjoint partial: Im<lam|X_a|psi>, a = register slot, into grad row g
     OP_GRADY = 5,  // adjoint partial: Im<lam|Y_a|psi>
     OP_GRADZ = 6,  // adjoint partial: Im<lam|Z_a|psi>, a = qubit-ref
-    OP_GRADP11 = 7 // adjoint partial: -2 Im<lam|P11(a,c)|psi>, a, c = qubit-refs
+    OP_GRADP11 = 7, // adjoint partial: -2 Im<lam|P11(a,c)|psi>, a, c = qubit-refs
+    // Cheaper forms chosen by the planner (same semantics as the general kind):
+    OP_MATR = 8,    // OP_MAT with a real matrix (H, RY, X)
+    OP_MATRX = 9,   // OP_MAT with real diagonal and imaginary off-diagonal entries (RX)
+    OP_DIAG1R = 10, // OP_DIAG1 whose qubit is register slot a
+    OP_DIAG2R = 11, // OP_DIAG2 with one qubit on register slot a, the other qubit-ref c
+    OP_DIAG2RR = 12 // OP_DIAG2 with both qubits on register slots a and c
 };
 
 // Qubit reference: r >= 0 is a tile position; r < 0 is global qubit (-1 - r), outside the tile.

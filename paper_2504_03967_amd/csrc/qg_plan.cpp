@@ -557,18 +557,56 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
                 op.kind = it.kind;
                 op.g = it.g;
                 std::memcpy(op.m, it.m, sizeof op.m);
+                // register slot of a qubit in this phase's layout, or -1
+                auto slot_of = [&](int qq) {
+                    if (pos_of[qq] < 0) return -1;
+                    auto f = std::find(S.begin(), S.end(), pos_of[qq]);
+                    return f == S.end() ? -1 : (int)(f - S.begin());
+                };
                 switch (it.kind) {
-                case OP_MAT: case OP_GRADX: case OP_GRADY:
+                case OP_MAT:
+                    op.a = slot;
+                    // m = {m00, m01, m10, m11} as (re, im) pairs
+                    if (it.m[1] == 0 && it.m[3] == 0 && it.m[5] == 0 && it.m[7] == 0)
+                        op.kind = OP_MATR;
+                    else if (it.m[1] == 0 && it.m[2] == 0 && it.m[4] == 0 && it.m[7] == 0)
+                        op.kind = OP_MATRX;
+                    break;
+                case OP_GRADX: case OP_GRADY:
                     op.a = slot;
                     break;
                 case OP_CX:
                     op.a = slot;
                     op.c = ref(it.qc);
                     break;
-                case OP_DIAG1: case OP_GRADZ:
+                case OP_DIAG1:
+                    if (slot_of(it.qa) >= 0) {
+                        op.kind = OP_DIAG1R;
+                        op.a = slot_of(it.qa);
+                    } else {
+                        op.a = ref(it.qa);
+                    }
+                    break;
+                case OP_GRADZ:
                     op.a = ref(it.qa);
                     break;
-                case OP_DIAG2: case OP_GRADP11:
+                case OP_DIAG2: {
+                    const int sa = slot_of(it.qa), sc = slot_of(it.qc);
+                    if (sa >= 0 && sc >= 0) {
+                        op.kind = OP_DIAG2RR;
+                        op.a = sa;
+                        op.c = sc;
+                    } else if (sa >= 0 || sc >= 0) {
+                        op.kind = OP_DIAG2R;
+                        op.a = sa >= 0 ? sa : sc;
+                        op.c = ref(sa >= 0 ? it.qc : it.qa);
+                    } else {
+                        op.a = ref(it.qa);
+                        op.c = ref(it.qc);
+                    }
+                    break;
+                }
+                case OP_GRADP11:
                     op.a = ref(it.qa);
                     op.c = ref(it.qc);
                     break;

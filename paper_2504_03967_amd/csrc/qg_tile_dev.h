@@ -124,6 +124,88 @@ __device__ __forceinline__ void apply_mat(C (&a)[NS][NR], const R (&m)[8]) {
         }
 }
 
+// Real matrix m = {m00, -, m01, -, m10, -, m11, -} on register slot J.
+template <int J, int NS, int NR, typename C, typename R>
+__device__ __forceinline__ void apply_matr(C (&a)[NS][NR], const R (&m)[8]) {
+    constexpr int jb = 1 << J;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int e = 0; e < NR; ++e) {
+            if (e & jb) continue;
+            const C v0 = a[s][e], v1 = a[s][e | jb];
+            a[s][e].x = m[0] * v0.x + m[2] * v1.x;
+            a[s][e].y = m[0] * v0.y + m[2] * v1.y;
+            a[s][e | jb].x = m[4] * v0.x + m[6] * v1.x;
+            a[s][e | jb].y = m[4] * v0.y + m[6] * v1.y;
+        }
+}
+
+// Real diagonal, imaginary off-diagonal: m = {m00, -, -, Im m01, -, Im m10, m11, -}.
+template <int J, int NS, int NR, typename C, typename R>
+__device__ __forceinline__ void apply_matrx(C (&a)[NS][NR], const R (&m)[8]) {
+    constexpr int jb = 1 << J;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int e = 0; e < NR; ++e) {
+            if (e & jb) continue;
+            const C v0 = a[s][e], v1 = a[s][e | jb];
+            a[s][e].x = m[0] * v0.x - m[3] * v1.y;
+            a[s][e].y = m[0] * v0.y + m[3] * v1.x;
+            a[s][e | jb].x = m[6] * v1.x - m[5] * v0.y;
+            a[s][e | jb].y = m[6] * v1.y + m[5] * v0.x;
+        }
+}
+
+// Diagonal 1-qubit op on register slot J: factor {m0, m1} where the bit is 0,
+// {m2, m3} where it is 1.
+template <int J, int NS, int NR, typename C, typename R>
+__device__ __forceinline__ void apply_diag1r(C (&a)[NS][NR], const R (&m)[8]) {
+    constexpr int jb = 1 << J;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int e = 0; e < NR; ++e) a[s][e] = (e & jb) ? cmul(a[s][e], m[2], m[3]) : cmul(a[s][e], m[0], m[1]);
+}
+
+// Phase {m0, m1} on the amplitudes whose register slots J and k are both 1
+// (k is uniform, so the factor of each amplitude is a scalar choice).
+template <int J, int NS, int NR, typename C, typename R>
+__device__ __forceinline__ void apply_diag2rk(C (&a)[NS][NR], const R (&m)[8], int k) {
+#pragma unroll
+    for (int e = 0; e < NR; ++e) {
+        if (!((e >> J) & 1)) continue;
+        const bool on = (e >> k) & 1;
+        const R re = on ? m[0] : (R)1, im = on ? m[1] : (R)0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a[s][e] = cmul(a[s][e], re, im);
+    }
+}
+
+// Multiplies the amplitudes whose register slot J is 1 by {re, im}.
+template <int J, int NS, int NR, typename C, typename R>
+__device__ __forceinline__ void apply_slot_factor(C (&a)[NS][NR], R re, R im) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int e = 0; e < NR; ++e)
+            if ((e >> J) & 1) a[s][e] = cmul(a[s][e], re, im);
+}
+
+// Slot dispatch: slots are < RB (the planner guarantees it).  A path that
+// leaves the registers untouched would make the compiler copy all of them
+// around every op, so impossible cases are marked unreachable.
+#define QG_SLOT_SWITCH(slot, CALL)                                                         \
+    switch (slot) {                                                                        \
+    case 0: { constexpr int J_ = 0; CALL; } break;                                         \
+    case 1: if constexpr (RB > 1) { constexpr int J_ = 1; CALL; } else __builtin_unreachable(); break; \
+    case 2: if constexpr (RB > 2) { constexpr int J_ = 2; CALL; } else __builtin_unreachable(); break; \
+    case 3: if constexpr (RB > 3) { constexpr int J_ = 3; CALL; } else __builtin_unreachable(); break; \
+    case 4: if constexpr (RB > 4) { constexpr int J_ = 4; CALL; } else __builtin_unreachable(); break; \
+    default: __builtin_unreachable();                                                      \
+    }
+
 // Controlled X: exchange the amplitudes of each pair on register slot J
 // where the control bit is 1.  cref >= 0 is the control's tile position;
 // otherwise the control lies outside the tile and fixed_on is its value there.
@@ -378,48 +460,43 @@ __device__ __forceinline__ void tile_phases(const PassDesc &P, const PhaseDesc *
             for (int k = 0; k < 8; ++k) m[k] = (R)op.m[k];
             const int kind = op.kind;
             if (kind == OP_MAT) {
-                switch (op.a) {
-                case 0: apply_mat<0>(a, m); break;
-                case 1: if constexpr (RB > 1) apply_mat<1>(a, m); else __builtin_unreachable(); break;
-                case 2: if constexpr (RB > 2) apply_mat<2>(a, m); else __builtin_unreachable(); break;
-                case 3: if constexpr (RB > 3) apply_mat<3>(a, m); else __builtin_unreachable(); break;
-                case 4: if constexpr (RB > 4) apply_mat<4>(a, m); else __builtin_unreachable(); break;
-                default: __builtin_unreachable();
-                }
+                QG_SLOT_SWITCH(op.a, (apply_mat<J_>(a, m)));
+            } else if (kind == OP_MATR) {
+                QG_SLOT_SWITCH(op.a, (apply_matr<J_>(a, m)));
+            } else if (kind == OP_MATRX) {
+                QG_SLOT_SWITCH(op.a, (apply_matrx<J_>(a, m)));
             } else if (kind == OP_CX) {
                 // A control outside the tile is constant over the tile; when it
-                // is 0 every select keeps the input (no branch: a path that
-                // leaves the registers untouched costs a copy of all of them).
+                // is 0 every select keeps the input (no branch, see above).
                 const bool fon = make_bit(op.c, gbase).fixed_one;
-                // Slots are < RB (checked by the planner); a path that leaves the
-                // registers untouched would make the compiler copy all of them.
-                switch (op.a) {
-                case 0: apply_cx<0>(a, tp, ep, op.c, fon); break;
-                case 1: if constexpr (RB > 1) apply_cx<1>(a, tp, ep, op.c, fon); else __builtin_unreachable(); break;
-                case 2: if constexpr (RB > 2) apply_cx<2>(a, tp, ep, op.c, fon); else __builtin_unreachable(); break;
-                case 3: if constexpr (RB > 3) apply_cx<3>(a, tp, ep, op.c, fon); else __builtin_unreachable(); break;
-                case 4: if constexpr (RB > 4) apply_cx<4>(a, tp, ep, op.c, fon); else __builtin_unreachable(); break;
-                default: __builtin_unreachable();
-                }
+                QG_SLOT_SWITCH(op.a, (apply_cx<J_>(a, tp, ep, op.c, fon)));
+            } else if (kind == OP_DIAG1R) {
+                QG_SLOT_SWITCH(op.a, (apply_diag1r<J_>(a, m)));
+            } else if (kind == OP_DIAG2RR) {
+                QG_SLOT_SWITCH(op.a, (apply_diag2rk<J_>(a, m, op.c)));
+            } else if (kind == OP_DIAG2R) {
+                // the other qubit is a thread bit or outside the tile: one
+                // factor per thread
+                const bool on = make_bit(op.c, gbase).of(tp);
+                const R re = on ? m[0] : (R)1, im = on ? m[1] : (R)0;
+                QG_SLOT_SWITCH(op.a, (apply_slot_factor<J_>(a, re, im)));
             } else if (kind == OP_DIAG1) {
-                const Bit ba = make_bit(op.a, gbase);
+                // thread bit or outside the tile: one factor per thread
+                const bool one = make_bit(op.a, gbase).of(tp);
+                const R re = one ? m[2] : m[0], im = one ? m[3] : m[1];
 #pragma unroll
-                for (int e = 0; e < NR; ++e) {
-                    const bool one = ba.of(tp | ep[e]);
-                    const R re = one ? m[2] : m[0], im = one ? m[3] : m[1];
+                for (int e = 0; e < NR; ++e)
 #pragma unroll
                     for (int s = 0; s < NS; ++s) a[s][e] = cmul(a[s][e], re, im);
-                }
             } else if (kind == OP_DIAG2) {
-                const Bit ba = make_bit(op.a, gbase), bc = make_bit(op.c, gbase);
+                const bool on = make_bit(op.a, gbase).of(tp) && make_bit(op.c, gbase).of(tp);
+                const R re = on ? m[0] : (R)1, im = on ? m[1] : (R)0;
 #pragma unroll
-                for (int e = 0; e < NR; ++e) {
-                    const bool both = ba.of(tp | ep[e]) && bc.of(tp | ep[e]);
+                for (int e = 0; e < NR; ++e)
 #pragma unroll
-                    for (int s = 0; s < NS; ++s) a[s][e] = sel(both, cmul(a[s][e], m[0], m[1]), a[s][e]);
-                }
+                    for (int s = 0; s < NS; ++s) a[s][e] = cmul(a[s][e], re, im);
             } else if constexpr (NS == 1) {
-                // gradient ops only occur in adjoint programs
+                __builtin_unreachable();  // gradient ops only occur in adjoint programs
             } else {
                 {
                     double acc = 0.0;
