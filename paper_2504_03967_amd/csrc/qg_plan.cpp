@@ -149,6 +149,127 @@ const Knob kKnobs[] = {
     {"pipe_min_ops", [](Tuning &t) { return &t.pipe_min_ops; }, 1, 1 << 20},
     {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 1, 1 << 30},
 };
+
+// A phase of a pass: the tile positions held in registers (slot order) and
+// the items it applies, in execution order.
+struct PhasePlan {
+    std::vector<int> S;
+    std::vector<int> items;
+};
+
+// Fills S up to rb positions with the highest positions not yet in it.
+void fill_slots(std::vector<int> *S, int b, int rb) {
+    for (int p = b - 1; p >= 0 && (int)S->size() < rb; --p)
+        if (std::find(S->begin(), S->end(), p) == S->end()) S->push_back(p);
+}
+
+// Items in their given order; a phase ends at the first item whose register
+// qubit is not among the first rb distinct ones (adjoint sweeps keep this
+// order: their gradient partials read the state at fixed points).
+std::vector<PhasePlan> plan_phases_in_order(const std::vector<Item> &items, const int *pos_of, int b, int rb) {
+    std::vector<PhasePlan> out;
+    size_t i = 0;
+    do {
+        PhasePlan pp;
+        for (size_t j = i; j < items.size() && (int)pp.S.size() < rb; ++j) {
+            const int q = needs_register(items[j]);
+            if (q < 0) continue;
+            if (std::find(pp.S.begin(), pp.S.end(), pos_of[q]) == pp.S.end()) pp.S.push_back(pos_of[q]);
+        }
+        fill_slots(&pp.S, b, rb);
+        for (; i < items.size(); ++i) {
+            const int q = needs_register(items[i]);
+            if (q >= 0 && std::find(pp.S.begin(), pp.S.end(), pos_of[q]) == pp.S.end()) break;
+            pp.items.push_back((int)i);
+        }
+        out.push_back(pp);
+    } while (i < items.size());
+    return out;
+}
+
+// Qubits an item acts on, and whether it is diagonal on each (a CX is
+// diagonal on its control).  Two items commute when every qubit they share is
+// one on which both are diagonal.
+int item_qubits(const Item &it, int *q, bool *diag) {
+    switch (it.kind) {
+    case OP_CX:
+        q[0] = it.qa, diag[0] = false;
+        q[1] = it.qc, diag[1] = true;
+        return 2;
+    case OP_DIAG1:
+        q[0] = it.qa, diag[0] = true;
+        return 1;
+    case OP_DIAG2:
+        q[0] = it.qa, diag[0] = true;
+        q[1] = it.qc, diag[1] = true;
+        return 2;
+    default:
+        q[0] = it.qa, diag[0] = false;
+        return 1;
+    }
+}
+
+bool items_commute(const Item &x, const Item &y) {
+    int qx[2], qy[2];
+    bool dx[2], dy[2];
+    const int nx = item_qubits(x, qx, dx), ny = item_qubits(y, qy, dy);
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            if (qx[i] == qy[j] && !(dx[i] && dy[j])) return false;
+    return true;
+}
+
+// Fewer register layouts (each change is an LDS exchange of the whole tile):
+// items may run in any order that keeps every non-commuting pair in its given
+// order.  A phase runs every ready item it can; when none is left it takes the
+// register qubit of the earliest ready item (for the first phase, one at or
+// above the cache-line bits if any, so that the loads stay line-aligned),
+// until rb qubits are held.
+std::vector<PhasePlan> plan_phases(const std::vector<Item> &items, const int *pos_of, int b, int rb, int line_bits) {
+    const int n = (int)items.size();
+    std::vector<std::vector<int>> pred(n);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < j; ++i)
+            if (!items_commute(items[i], items[j])) pred[j].push_back(i);
+    std::vector<char> done(n, 0);
+    int left = n;
+    auto ready = [&](int j) {
+        if (done[j]) return false;
+        for (int i : pred[j])
+            if (!done[i]) return false;
+        return true;
+    };
+    std::vector<PhasePlan> out;
+    do {
+        PhasePlan pp;
+        for (;;) {
+            bool progress = true;
+            while (progress) {
+                progress = false;
+                for (int j = 0; j < n; ++j) {
+                    if (!ready(j)) continue;
+                    const int q = needs_register(items[j]);
+                    if (q >= 0 && std::find(pp.S.begin(), pp.S.end(), pos_of[q]) == pp.S.end()) continue;
+                    done[j] = 1;
+                    --left;
+                    pp.items.push_back(j);
+                    progress = true;
+                }
+            }
+            if (left == 0 || (int)pp.S.size() >= rb) break;
+            int pick = -1;
+            for (int j = 0; j < n && pick < 0; ++j)
+                if (ready(j) && (!out.empty() || pos_of[needs_register(items[j])] >= line_bits)) pick = j;
+            for (int j = 0; j < n && pick < 0; ++j)
+                if (ready(j)) pick = j;
+            if (pick < 0) break;
+            pp.S.push_back(pos_of[needs_register(items[pick])]);
+        }
+        fill_slots(&pp.S, b, rb);
+        out.push_back(pp);
+    } while (left > 0);
+    return out;
+}
 }  // namespace
 
 int pass_class(uint64_t required, bool c64) {
@@ -518,19 +639,12 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
         pd.phase_begin = (int)prog.phases.size();
 
         // ---- phases: register positions must hold every mixing op's target
+        const int line_bits = cfg.c64 ? 4 : 3;
+        const std::vector<PhasePlan> plans =
+            cfg.reverse ? plan_phases_in_order(items, pos_of, b, rb) : plan_phases(items, pos_of, b, rb, line_bits);
         auto ref = [&](int q) { return pos_of[q] >= 0 ? pos_of[q] : qref_global(q); };
-        size_t i = 0;
-        bool first = true;
-        while (i < items.size() || first) {
-            std::vector<int> S;
-            for (size_t j = i; j < items.size() && (int)S.size() < rb; ++j) {
-                int q = needs_register(items[j]);
-                if (q < 0) continue;
-                int p = pos_of[q];
-                if (std::find(S.begin(), S.end(), p) == S.end()) S.push_back(p);
-            }
-            for (int p = b - 1; p >= 0 && (int)S.size() < rb; --p)
-                if (std::find(S.begin(), S.end(), p) == S.end()) S.push_back(p);
+        for (const PhasePlan &pp : plans) {
+            const std::vector<int> &S = pp.S;
             PhaseDesc ph{};
             std::vector<int> thr;
             for (int p = 0; p < b; ++p)
@@ -544,25 +658,20 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
                 ph.reg_poff[j] = 1u << S[j];
             }
             ph.op_begin = (int)prog.ops.size();
-            for (; i < items.size(); ++i) {
-                const Item &it = items[i];
+            // register slot of a qubit in this phase's layout, or -1
+            auto slot_of = [&](int qq) {
+                if (pos_of[qq] < 0) return -1;
+                auto f = std::find(S.begin(), S.end(), pos_of[qq]);
+                return f == S.end() ? -1 : (int)(f - S.begin());
+            };
+            for (int ii : pp.items) {
+                const Item &it = items[ii];
                 const int q = needs_register(it);
-                int slot = -1;
-                if (q >= 0) {
-                    auto f = std::find(S.begin(), S.end(), pos_of[q]);
-                    if (f == S.end()) break;  // next phase
-                    slot = (int)(f - S.begin());
-                }
+                const int slot = q >= 0 ? slot_of(q) : -1;
                 DevOp op{};
                 op.kind = it.kind;
                 op.g = it.g;
                 std::memcpy(op.m, it.m, sizeof op.m);
-                // register slot of a qubit in this phase's layout, or -1
-                auto slot_of = [&](int qq) {
-                    if (pos_of[qq] < 0) return -1;
-                    auto f = std::find(S.begin(), S.end(), pos_of[qq]);
-                    return f == S.end() ? -1 : (int)(f - S.begin());
-                };
                 switch (it.kind) {
                 case OP_MAT:
                     op.a = slot;
@@ -615,7 +724,6 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
             }
             ph.op_end = (int)prog.ops.size();
             prog.phases.push_back(ph);
-            first = false;
         }
         pd.n_phase = (int)prog.phases.size() - pd.phase_begin;
         const int n_ops = prog.phases.back().op_end - prog.phases[pd.phase_begin].op_begin;
@@ -625,7 +733,6 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
         // covers whole 128-byte lines: the first and last layouts must keep the
         // line-offset tile positions (3 for complex128, 4 for complex64) on lanes.
         if ((pd.flags & PASS_NT) && cfg.nt_mode == 1) {
-            const int line_bits = cfg.c64 ? 4 : 3;
             const uint32_t line_mask = (1u << std::min(line_bits, b)) - 1;
             for (int which : {pd.phase_begin, pd.phase_begin + pd.n_phase - 1}) {
                 const PhaseDesc &ph = prog.phases[which];

@@ -439,18 +439,31 @@ __device__ __forceinline__ void tile_phases(const PassDesc &P, const PhaseDesc *
         for (int e = 0; e < NR; ++e) ep[e] = elem_poff<RB>(ph, e);
         if (p > 0) {
             // Move the tile into the new register layout through LDS.
+            // The slot map is XOR-linear and thread and register offsets have
+            // disjoint bits, so swz(t | r) = swz(t) ^ swz(r): one per-thread
+            // term and one uniform (scalar) term per element.
+            // (readfirstlane keeps the uniform term from being folded back into
+            // the per-thread expression.)  Offsets are in bytes.
             const PhaseDesc &prev = phases[p - 1];
-            const uint32_t tq = thread_poff(prev, tb, tid);
+            constexpr uint32_t SZ = sizeof(C);
+            const uint32_t sq = swz<R>(thread_poff(prev, tb, tid)) * SZ, sp = swz<R>(tp) * SZ;
+            unsigned char *lb = reinterpret_cast<unsigned char *>(lds);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 __syncthreads();
                 if (active) {
 #pragma unroll
-                    for (int e = 0; e < NR; ++e) lds[swz<R>(tq | elem_poff<RB>(prev, e))] = a[s][e];
+                    for (int e = 0; e < NR; ++e) {
+                        const uint32_t u = __builtin_amdgcn_readfirstlane(swz<R>(elem_poff<RB>(prev, e)) * SZ);
+                        *reinterpret_cast<C *>(lb + (sq ^ u)) = a[s][e];
+                    }
                 }
                 __syncthreads();
 #pragma unroll
-                for (int e = 0; e < NR; ++e) a[s][e] = lds[swz<R>(tp | ep[e])];
+                for (int e = 0; e < NR; ++e) {
+                    const uint32_t u = __builtin_amdgcn_readfirstlane(swz<R>(ep[e]) * SZ);
+                    a[s][e] = *reinterpret_cast<const C *>(lb + (sp ^ u));
+                }
             }
         }
         for (int i = ph.op_begin; i < ph.op_end; ++i) {
