@@ -111,8 +111,9 @@ __device__ __forceinline__ double im_conj_mul(C l, C p) {
     return (double)l.x * p.y - (double)l.y * p.x;
 }
 
+// The register ops read `a` and write every element of `o` (o may be a).
 template <int J, int NS, int NR, typename C, typename R>
-__device__ __forceinline__ void apply_mat(C (&a)[NS][NR], const R (&m)[8]) {
+__device__ __forceinline__ void apply_mat(const C (&a)[NS][NR], C (&o)[NS][NR], const R (&m)[8]) {
     constexpr int jb = 1 << J;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
@@ -120,13 +121,13 @@ __device__ __forceinline__ void apply_mat(C (&a)[NS][NR], const R (&m)[8]) {
         for (int e = 0; e < NR; ++e) {
             if (e & jb) continue;
             const C v0 = a[s][e], v1 = a[s][e | jb];
-            mat2(m, v0, v1, a[s][e], a[s][e | jb]);
+            mat2(m, v0, v1, o[s][e], o[s][e | jb]);
         }
 }
 
 // Real matrix m = {m00, -, m01, -, m10, -, m11, -} on register slot J.
 template <int J, int NS, int NR, typename C, typename R>
-__device__ __forceinline__ void apply_matr(C (&a)[NS][NR], const R (&m)[8]) {
+__device__ __forceinline__ void apply_matr(const C (&a)[NS][NR], C (&o)[NS][NR], const R (&m)[8]) {
     constexpr int jb = 1 << J;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
@@ -134,16 +135,16 @@ __device__ __forceinline__ void apply_matr(C (&a)[NS][NR], const R (&m)[8]) {
         for (int e = 0; e < NR; ++e) {
             if (e & jb) continue;
             const C v0 = a[s][e], v1 = a[s][e | jb];
-            a[s][e].x = m[0] * v0.x + m[2] * v1.x;
-            a[s][e].y = m[0] * v0.y + m[2] * v1.y;
-            a[s][e | jb].x = m[4] * v0.x + m[6] * v1.x;
-            a[s][e | jb].y = m[4] * v0.y + m[6] * v1.y;
+            o[s][e].x = m[0] * v0.x + m[2] * v1.x;
+            o[s][e].y = m[0] * v0.y + m[2] * v1.y;
+            o[s][e | jb].x = m[4] * v0.x + m[6] * v1.x;
+            o[s][e | jb].y = m[4] * v0.y + m[6] * v1.y;
         }
 }
 
 // Real diagonal, imaginary off-diagonal: m = {m00, -, -, Im m01, -, Im m10, m11, -}.
 template <int J, int NS, int NR, typename C, typename R>
-__device__ __forceinline__ void apply_matrx(C (&a)[NS][NR], const R (&m)[8]) {
+__device__ __forceinline__ void apply_matrx(const C (&a)[NS][NR], C (&o)[NS][NR], const R (&m)[8]) {
     constexpr int jb = 1 << J;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
@@ -151,46 +152,49 @@ __device__ __forceinline__ void apply_matrx(C (&a)[NS][NR], const R (&m)[8]) {
         for (int e = 0; e < NR; ++e) {
             if (e & jb) continue;
             const C v0 = a[s][e], v1 = a[s][e | jb];
-            a[s][e].x = m[0] * v0.x - m[3] * v1.y;
-            a[s][e].y = m[0] * v0.y + m[3] * v1.x;
-            a[s][e | jb].x = m[6] * v1.x - m[5] * v0.y;
-            a[s][e | jb].y = m[6] * v1.y + m[5] * v0.x;
+            o[s][e].x = m[0] * v0.x - m[3] * v1.y;
+            o[s][e].y = m[0] * v0.y + m[3] * v1.x;
+            o[s][e | jb].x = m[6] * v1.x - m[5] * v0.y;
+            o[s][e | jb].y = m[6] * v1.y + m[5] * v0.x;
         }
 }
 
 // Diagonal 1-qubit op on register slot J: factor {m0, m1} where the bit is 0,
 // {m2, m3} where it is 1.
 template <int J, int NS, int NR, typename C, typename R>
-__device__ __forceinline__ void apply_diag1r(C (&a)[NS][NR], const R (&m)[8]) {
+__device__ __forceinline__ void apply_diag1r(const C (&a)[NS][NR], C (&o)[NS][NR], const R (&m)[8]) {
     constexpr int jb = 1 << J;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int e = 0; e < NR; ++e) a[s][e] = (e & jb) ? cmul(a[s][e], m[2], m[3]) : cmul(a[s][e], m[0], m[1]);
+        for (int e = 0; e < NR; ++e) o[s][e] = (e & jb) ? cmul(a[s][e], m[2], m[3]) : cmul(a[s][e], m[0], m[1]);
 }
 
 // Phase {m0, m1} on the amplitudes whose register slots J and k are both 1
 // (k is uniform, so the factor of each amplitude is a scalar choice).
 template <int J, int NS, int NR, typename C, typename R>
-__device__ __forceinline__ void apply_diag2rk(C (&a)[NS][NR], const R (&m)[8], int k) {
+__device__ __forceinline__ void apply_diag2rk(const C (&a)[NS][NR], C (&o)[NS][NR], const R (&m)[8], int k) {
 #pragma unroll
     for (int e = 0; e < NR; ++e) {
-        if (!((e >> J) & 1)) continue;
+        if (!((e >> J) & 1)) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) o[s][e] = a[s][e];
+            continue;
+        }
         const bool on = (e >> k) & 1;
         const R re = on ? m[0] : (R)1, im = on ? m[1] : (R)0;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) a[s][e] = cmul(a[s][e], re, im);
+        for (int s = 0; s < NS; ++s) o[s][e] = cmul(a[s][e], re, im);
     }
 }
 
 // Multiplies the amplitudes whose register slot J is 1 by {re, im}.
 template <int J, int NS, int NR, typename C, typename R>
-__device__ __forceinline__ void apply_slot_factor(C (&a)[NS][NR], R re, R im) {
+__device__ __forceinline__ void apply_slot_factor(const C (&a)[NS][NR], C (&o)[NS][NR], R re, R im) {
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int e = 0; e < NR; ++e)
-            if ((e >> J) & 1) a[s][e] = cmul(a[s][e], re, im);
+        for (int e = 0; e < NR; ++e) o[s][e] = ((e >> J) & 1) ? cmul(a[s][e], re, im) : a[s][e];
 }
 
 // Slot dispatch: slots are < RB (the planner guarantees it).  A path that
@@ -210,8 +214,8 @@ __device__ __forceinline__ void apply_slot_factor(C (&a)[NS][NR], R re, R im) {
 // where the control bit is 1.  cref >= 0 is the control's tile position;
 // otherwise the control lies outside the tile and fixed_on is its value there.
 template <int J, int NS, int NR, typename C>
-__device__ __forceinline__ void apply_cx(C (&a)[NS][NR], uint32_t tp, const uint32_t (&ep)[NR], int cref,
-                                         bool fixed_on) {
+__device__ __forceinline__ void apply_cx(const C (&a)[NS][NR], C (&o)[NS][NR], uint32_t tp, const uint32_t (&ep)[NR],
+                                         int cref, bool fixed_on) {
     constexpr int jb = 1 << J;
     const uint32_t cm = cref >= 0 ? (1u << cref) : 0u;
 #pragma unroll
@@ -221,8 +225,8 @@ __device__ __forceinline__ void apply_cx(C (&a)[NS][NR], uint32_t tp, const uint
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const C x = a[s][e], y = a[s][e | jb];
-            a[s][e] = sel(on, y, x);
-            a[s][e | jb] = sel(on, x, y);
+            o[s][e] = sel(on, y, x);
+            o[s][e | jb] = sel(on, x, y);
         }
     }
 }
@@ -259,17 +263,6 @@ __device__ __forceinline__ void dispatch_mat(int slot, C (&a)[NS][1 << RB], cons
     } else {
         if (slot == J) apply_mat<J>(a, m);
         else dispatch_mat<J + 1, RB>(slot, a, m);
-    }
-}
-
-template <int J, int RB, int NS, typename C>
-__device__ __forceinline__ void dispatch_cx(int slot, C (&a)[NS][1 << RB], uint32_t tp,
-                                            const uint32_t (&ep)[1 << RB], int cref, bool fixed_on) {
-    if constexpr (J == RB - 1) {
-        apply_cx<J>(a, tp, ep, cref, fixed_on);
-    } else {
-        if (slot == J) apply_cx<J>(a, tp, ep, cref, fixed_on);
-        else dispatch_cx<J + 1, RB>(slot, a, tp, ep, cref, fixed_on);
     }
 }
 
@@ -419,6 +412,93 @@ __device__ __forceinline__ double tile_obs_terms(const PassDesc &P, const PhaseD
     return acc;
 }
 
+// One op of a phase: reads the registers `a`, writes every element of `o`
+// (o may be a); gradient ops (adjoint sweeps) also write their per-wave
+// partial sum and copy a to o.
+template <typename R, int RB, int NS>
+__device__ __forceinline__ void apply_op(const DevOp &op, const typename V2<R>::T (&a)[NS][1 << RB],
+                                         typename V2<R>::T (&o)[NS][1 << RB], uint64_t gbase, uint32_t tp,
+                                         const uint32_t (&ep)[1 << RB], double *__restrict__ gpart,
+                                         int64_t gstride, uint64_t tile_idx, int tid) {
+    constexpr int NR = 1 << RB;
+    R m[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m[k] = (R)op.m[k];
+    const int kind = op.kind;
+    if (kind == OP_MAT) {
+        QG_SLOT_SWITCH(op.a, (apply_mat<J_>(a, o, m)));
+    } else if (kind == OP_MATR) {
+        QG_SLOT_SWITCH(op.a, (apply_matr<J_>(a, o, m)));
+    } else if (kind == OP_MATRX) {
+        QG_SLOT_SWITCH(op.a, (apply_matrx<J_>(a, o, m)));
+    } else if (kind == OP_CX) {
+        // A control outside the tile is constant over the tile; when it
+        // is 0 every select keeps the input (no branch: a path that leaves the
+        // registers untouched makes the compiler copy all of them).
+        const bool fon = make_bit(op.c, gbase).fixed_one;
+        QG_SLOT_SWITCH(op.a, (apply_cx<J_>(a, o, tp, ep, op.c, fon)));
+    } else if (kind == OP_DIAG1R) {
+        QG_SLOT_SWITCH(op.a, (apply_diag1r<J_>(a, o, m)));
+    } else if (kind == OP_DIAG2RR) {
+        QG_SLOT_SWITCH(op.a, (apply_diag2rk<J_>(a, o, m, op.c)));
+    } else if (kind == OP_DIAG2R) {
+        // the other qubit is a thread bit or outside the tile: one
+        // factor per thread
+        const bool on = make_bit(op.c, gbase).of(tp);
+        const R re = on ? m[0] : (R)1, im = on ? m[1] : (R)0;
+        QG_SLOT_SWITCH(op.a, (apply_slot_factor<J_>(a, o, re, im)));
+    } else if (kind == OP_DIAG1) {
+        // thread bit or outside the tile: one factor per thread
+        const bool one = make_bit(op.a, gbase).of(tp);
+        const R re = one ? m[2] : m[0], im = one ? m[3] : m[1];
+#pragma unroll
+        for (int e = 0; e < NR; ++e)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) o[s][e] = cmul(a[s][e], re, im);
+    } else if (kind == OP_DIAG2) {
+        const bool on = make_bit(op.a, gbase).of(tp) && make_bit(op.c, gbase).of(tp);
+        const R re = on ? m[0] : (R)1, im = on ? m[1] : (R)0;
+#pragma unroll
+        for (int e = 0; e < NR; ++e)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) o[s][e] = cmul(a[s][e], re, im);
+    } else if constexpr (NS == 1) {
+        __builtin_unreachable();  // gradient ops only occur in adjoint programs
+    } else {
+        {
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int e = 0; e < NR; ++e) o[s][e] = a[s][e];
+            double acc = 0.0;
+            if (kind == OP_GRADZ) {
+                const Bit ba = make_bit(op.a, gbase);
+#pragma unroll
+                for (int e = 0; e < NR; ++e) {
+                    const double v = im_conj_mul(a[1][e], a[0][e]);
+                    acc += ba.of(tp | ep[e]) ? -v : v;
+                }
+            } else if (kind == OP_GRADP11) {
+                const Bit ba = make_bit(op.a, gbase), bc = make_bit(op.c, gbase);
+#pragma unroll
+                for (int e = 0; e < NR; ++e) {
+                    const double v = im_conj_mul(a[1][e], a[0][e]);
+                    acc += (ba.of(tp | ep[e]) && bc.of(tp | ep[e])) ? -2.0 * v : 0.0;
+                }
+            } else {
+                const bool isy = kind == OP_GRADY;
+                acc = dispatch_grad_xy<0, RB>(op.a, a, isy);
+            }
+            const int width = blockDim.x < 64 ? (int)blockDim.x : 64;
+            acc = wave_sum(acc, width);
+            if ((tid & (width - 1)) == 0) {
+                const int waves = (blockDim.x + 63) / 64;
+                gpart[(int64_t)op.g * gstride + (int64_t)tile_idx * waves + tid / 64] = acc;
+            }
+        }
+    }
+}
+
 // Runs every phase of a pass on the registers: LDS exchanges between layouts,
 // then the phase's ops.  `active` is false for threads beyond the tile's 2^tb.
 template <typename R, int RB, int NS>
@@ -466,80 +546,16 @@ __device__ __forceinline__ void tile_phases(const PassDesc &P, const PhaseDesc *
                 }
             }
         }
-        for (int i = ph.op_begin; i < ph.op_end; ++i) {
-            const DevOp &op = ops[i];
-            R m[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) m[k] = (R)op.m[k];
-            const int kind = op.kind;
-            if (kind == OP_MAT) {
-                QG_SLOT_SWITCH(op.a, (apply_mat<J_>(a, m)));
-            } else if (kind == OP_MATR) {
-                QG_SLOT_SWITCH(op.a, (apply_matr<J_>(a, m)));
-            } else if (kind == OP_MATRX) {
-                QG_SLOT_SWITCH(op.a, (apply_matrx<J_>(a, m)));
-            } else if (kind == OP_CX) {
-                // A control outside the tile is constant over the tile; when it
-                // is 0 every select keeps the input (no branch, see above).
-                const bool fon = make_bit(op.c, gbase).fixed_one;
-                QG_SLOT_SWITCH(op.a, (apply_cx<J_>(a, tp, ep, op.c, fon)));
-            } else if (kind == OP_DIAG1R) {
-                QG_SLOT_SWITCH(op.a, (apply_diag1r<J_>(a, m)));
-            } else if (kind == OP_DIAG2RR) {
-                QG_SLOT_SWITCH(op.a, (apply_diag2rk<J_>(a, m, op.c)));
-            } else if (kind == OP_DIAG2R) {
-                // the other qubit is a thread bit or outside the tile: one
-                // factor per thread
-                const bool on = make_bit(op.c, gbase).of(tp);
-                const R re = on ? m[0] : (R)1, im = on ? m[1] : (R)0;
-                QG_SLOT_SWITCH(op.a, (apply_slot_factor<J_>(a, re, im)));
-            } else if (kind == OP_DIAG1) {
-                // thread bit or outside the tile: one factor per thread
-                const bool one = make_bit(op.a, gbase).of(tp);
-                const R re = one ? m[2] : m[0], im = one ? m[3] : m[1];
-#pragma unroll
-                for (int e = 0; e < NR; ++e)
-#pragma unroll
-                    for (int s = 0; s < NS; ++s) a[s][e] = cmul(a[s][e], re, im);
-            } else if (kind == OP_DIAG2) {
-                const bool on = make_bit(op.a, gbase).of(tp) && make_bit(op.c, gbase).of(tp);
-                const R re = on ? m[0] : (R)1, im = on ? m[1] : (R)0;
-#pragma unroll
-                for (int e = 0; e < NR; ++e)
-#pragma unroll
-                    for (int s = 0; s < NS; ++s) a[s][e] = cmul(a[s][e], re, im);
-            } else if constexpr (NS == 1) {
-                __builtin_unreachable();  // gradient ops only occur in adjoint programs
-            } else {
-                {
-                    double acc = 0.0;
-                    if (kind == OP_GRADZ) {
-                        const Bit ba = make_bit(op.a, gbase);
-#pragma unroll
-                        for (int e = 0; e < NR; ++e) {
-                            const double v = im_conj_mul(a[1][e], a[0][e]);
-                            acc += ba.of(tp | ep[e]) ? -v : v;
-                        }
-                    } else if (kind == OP_GRADP11) {
-                        const Bit ba = make_bit(op.a, gbase), bc = make_bit(op.c, gbase);
-#pragma unroll
-                        for (int e = 0; e < NR; ++e) {
-                            const double v = im_conj_mul(a[1][e], a[0][e]);
-                            acc += (ba.of(tp | ep[e]) && bc.of(tp | ep[e])) ? -2.0 * v : 0.0;
-                        }
-                    } else {
-                        const bool isy = kind == OP_GRADY;
-                        acc = dispatch_grad_xy<0, RB>(op.a, a, isy);
-                    }
-                    const int width = blockDim.x < 64 ? (int)blockDim.x : 64;
-                    acc = wave_sum(acc, width);
-                    if ((tid & (width - 1)) == 0) {
-                        const int waves = (blockDim.x + 63) / 64;
-                        gpart[(int64_t)op.g * gstride + (int64_t)tile_idx * waves + tid / 64] = acc;
-                    }
-                }
-            }
+        // Each op reads one register set and writes the other, so that no op
+        // has to update its inputs in place (which costs a copy of every
+        // register per op at the loop's back edge).
+        C b[NS][NR];
+        int i = ph.op_begin;
+        for (; i + 1 < ph.op_end; i += 2) {
+            apply_op<R, RB, NS>(ops[i], a, b, gbase, tp, ep, gpart, gstride, tile_idx, tid);
+            apply_op<R, RB, NS>(ops[i + 1], b, a, gbase, tp, ep, gpart, gstride, tile_idx, tid);
         }
+        if (i < ph.op_end) apply_op<R, RB, NS>(ops[i], a, a, gbase, tp, ep, gpart, gstride, tile_idx, tid);
     }
 }
 
