@@ -20,9 +20,9 @@ from . import workloads as W
 
 
 def _config_knobs(dtype: str, k: int) -> Dict[str, int]:
-    tile = 12 if dtype == "c128" else 13
-    high = 4 + k
     d = "c128" if dtype == "c128" else "c64"
+    tile = int(qg.get_tuning(f"tile_bits_{d}"))
+    high = 4 + k
     return {f"tile_bits_{d}": tile, f"max_high_{d}": high, f"low_bits_{d}": tile - high}
 
 

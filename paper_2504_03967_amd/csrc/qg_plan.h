@@ -44,9 +44,13 @@ int pass_class(uint64_t required, bool c64);
 // Process-wide tuning of the planner (defaults measured on MI355X; set by
 // qg_set_tuning or the autotuner).
 struct Tuning {
-    int tile_bits[2] = {12, 13};  // [c128, c64]
-    int reg_bits[2] = {4, 5};
-    int low_bits[2] = {7, 8};
+    // Fused passes: [c128, c64].  Measured on config-3, QFT and ansatz circuits:
+    // complex64 runs faster with 2^12-amplitude tiles and 16 registers per
+    // thread than with 2^13 and 32 (two workgroups per CU either way, shorter
+    // exchanges, lower register pressure).
+    int tile_bits[2] = {12, 12};
+    int reg_bits[2] = {4, 4};
+    int low_bits[2] = {7, 7};
     int max_high[2] = {5, 5};
     int nt = 1;
     int swz_bits = 4;
