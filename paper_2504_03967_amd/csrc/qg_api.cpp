@@ -175,7 +175,10 @@ bool fits_inline(const Program &prog, const PassDesc &pd) {
     if ((pd.flags & PASS_DENSE) || pd.n_phase > kInlinePhases) return false;
     const PhaseDesc &first = prog.phases[pd.phase_begin];
     const PhaseDesc &last = prog.phases[pd.phase_begin + pd.n_phase - 1];
-    return last.op_end - first.op_begin <= kInlineOps;
+    if (last.op_end - first.op_begin > kInlineOps) return false;
+    for (int i = first.op_begin; i < last.op_end; ++i)
+        if (prog.ops[i].kind == OP_DIAGRUN) return false;  // its tables live in the device program
+    return true;
 }
 
 void make_inline(const Program &prog, const PassDesc &pd, InlineProg *out) {
@@ -198,7 +201,7 @@ qg_status run_program(Ctx &cx, bool c64, const Program &prog, void *psi, void *l
     if (prog.passes.empty()) return QG_OK;
     bool need_upload = false;
     for (const PassDesc &pd : prog.passes) need_upload |= !fits_inline(prog, pd);
-    size_t pass_off = 0, phase_off = 0, op_off = 0, ut_off = 0;
+    size_t pass_off = 0, phase_off = 0, op_off = 0, ut_off = 0, run_off = 0, entry_off = 0;
     unsigned char *dev = nullptr;
     const size_t ut_size = c64 ? sizeof(float) : sizeof(double);
     if (need_upload) {
@@ -206,6 +209,8 @@ qg_status run_program(Ctx &cx, bool c64, const Program &prog, void *psi, void *l
         pass_off = pk.add(prog.passes);
         phase_off = pk.add(prog.phases);
         op_off = pk.add(prog.ops);
+        run_off = pk.add(prog.runs);
+        entry_off = pk.add(prog.entries);
         if (c64) {
             std::vector<float> f(prog.dense_ut.begin(), prog.dense_ut.end());
             ut_off = pk.add(f);
@@ -239,8 +244,10 @@ qg_status run_program(Ctx &cx, bool c64, const Program &prog, void *psi, void *l
         const int64_t gstride = (int64_t)pd.n_tiles * waves;
         const bool small = fits_inline(prog, pd);
         if (small) make_inline(prog, pd, &inl);
-        HIP_TRY(launch_tile(c64, pd, small ? &inl : nullptr, dev, pass_off, phase_off, op_off, (int)p, ns, psi, lam,
-                            gpart, gstride, cx.stream),
+        const ProgOffsets offs{(uint32_t)pass_off, (uint32_t)phase_off, (uint32_t)op_off, (uint32_t)run_off,
+                               (uint32_t)entry_off};
+        HIP_TRY(launch_tile(c64, pd, small ? &inl : nullptr, dev, offs, (int)p, ns, psi, lam, gpart, gstride,
+                            cx.stream),
                 "tile kernel launch");
         if (ns == 2 && pd.n_grad > 0) {
             HIP_TRY(launch_grad_rows(gpart, gstride, gstride, pd.n_grad, rows_out + pd.grad_base, cx.stream),
@@ -289,6 +296,7 @@ PlanConfig batch_config(int n, bool c64) {
     cfg.swz_bits = 0;
     cfg.max_gates_per_pass = n <= cfg.tile_bits ? (1 << 30) : 4096;
     cfg.use_classes = false;  // the persistent kernel is built for one register width
+    cfg.diag_run_min = 0;     // its programs carry no fused diagonal runs
     clamp_config(&cfg);
     return cfg;
 }

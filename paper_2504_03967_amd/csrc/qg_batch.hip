@@ -70,7 +70,7 @@ k_batch(const BatchCirc *__restrict__ circs, const int32_t *__restrict__ order, 
                 C a[1][1 << RB];
                 if (one_tile) tile_zero<R, RB>(P, ph[0], gbase, a, tid);
                 else if (active) tile_load<R, RB, 1>(P, ph[0], gbase, st, a, tid);
-                tile_phases<R, RB, 1>(P, ph, ops, gbase, a, lds, nullptr, 0, t, tid, active);
+                tile_phases<R, RB, 1>(P, ph, ops, DiagTables{nullptr, nullptr}, gbase, a, lds, nullptr, 0, t, tid, active);
                 const PhaseDesc &last = ph[P.n_phase - 1];
                 if (one_tile) {
                     if (active)

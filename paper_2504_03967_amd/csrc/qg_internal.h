@@ -34,11 +34,38 @@ enum OpKind : int32_t {
     OP_MATRX = 9,   // OP_MAT with real diagonal and imaginary off-diagonal entries (RX)
     OP_DIAG1R = 10, // OP_DIAG1 whose qubit is register slot a
     OP_DIAG2R = 11, // OP_DIAG2 with one qubit on register slot a, the other qubit-ref c
-    OP_DIAG2RR = 12 // OP_DIAG2 with both qubits on register slots a and c
+    OP_DIAG2RR = 12,// OP_DIAG2 with both qubits on register slots a and c
+    OP_DIAGRUN = 13 // a run of diagonal ops fused into one factor per amplitude: DiagRun a
 };
 
 // Qubit reference: r >= 0 is a tile position; r < 0 is global qubit (-1 - r), outside the tile.
 constexpr int qref_global(int q) { return -1 - q; }
+
+// A run of consecutive diagonal ops of one phase (OP_DIAGRUN), as one factor
+// per amplitude:  F = tf * prod_{register slot j set} r_j * prod_{slots j<k set} q_jk
+// where tf starts at c0 and r_j at r[j] (the uniform parts, computed on the
+// host), and each entry multiplies tf (entries [e_begin, s_begin[0])) or r_j
+// (entries [s_begin[j], s_begin[j+1])) by f1 where its condition holds, else
+// by f0.  The condition reads thread bits or qubits outside the tile only:
+// bit of ref a, and also of ref c when c != kNoRef.
+constexpr int32_t kNoRef = 1 << 30;
+struct DiagEntry {
+    int32_t a, c;
+    int32_t pad[2];
+    double f0[2], f1[2];
+};
+struct DiagRun {
+    double c0[2];
+    double r[kMaxRegBits][2];
+    double q[kMaxRegBits * (kMaxRegBits - 1) / 2][2];  // pair (j, k), j < k: index k (k - 1) / 2 + j
+    int32_t e_begin;
+    int32_t s_begin[kMaxRegBits + 1];
+};
+
+// Byte offsets of a program's arrays in its device copy.
+struct ProgOffsets {
+    uint32_t pass, phase, op, run, entry;
+};
 
 struct DevOp {
     int32_t kind;

@@ -15,8 +15,8 @@ namespace qg {
 // When `inl` is not NULL the pass travels by value as the kernel argument and
 // `dev` is not read.
 hipError_t launch_tile(bool c64, const PassDesc &host_pass, const InlineProg *inl, const void *dev,
-                       size_t pass_off, size_t phase_off, size_t op_off, int pass_idx, int ns,
-                       void *psi, void *lam, double *gpart, int64_t gstride, hipStream_t st);
+                       const ProgOffsets &offs, int pass_idx, int ns, void *psi, void *lam, double *gpart,
+                       int64_t gstride, hipStream_t st);
 
 // psi <- |0...0>
 hipError_t launch_zero_state(bool c64, void *psi, uint64_t dim, hipStream_t st);

@@ -146,6 +146,7 @@ const Knob kKnobs[] = {
     {"swz_bits", [](Tuning &t) { return &t.swz_bits; }, 0, 16},
     {"xcd", [](Tuning &t) { return &t.xcd; }, 0, 1},
     {"pipe", [](Tuning &t) { return &t.pipe; }, 0, 2},
+    {"diag_run_min", [](Tuning &t) { return &t.diag_run_min; }, 0, 1 << 20},
     {"pipe_min_ops", [](Tuning &t) { return &t.pipe_min_ops; }, 1, 1 << 20},
     {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 1, 1 << 30},
 };
@@ -357,6 +358,7 @@ PlanConfig default_config(int n, bool c64, int fusion) {
     c.nt_mode = t.nt;
     c.swz_bits = t.swz_bits;
     c.dense_min_gates = t.dense_min_gates;
+    c.diag_run_min = t.diag_run_min;
     return c;
 }
 
@@ -554,6 +556,70 @@ std::vector<Gate> permute(const std::vector<Gate> &g, const std::vector<int> &or
     return out;
 }
 
+// Fuses the diagonal items `run` (in order) of a phase into one DiagRun: the
+// uniform parts (register slots only) are multiplied out here in FP64, the
+// parts that read thread bits or qubits outside the tile become entries.
+template <typename SlotOf, typename Ref>
+void append_diag_run(const std::vector<Item> &items, const std::vector<int> &run, int rb, SlotOf slot_of, Ref ref,
+                     Program *prog) {
+    cd s0[kMaxRegBits], s1[kMaxRegBits], q[kMaxRegBits * (kMaxRegBits - 1) / 2];
+    for (auto &v : s0) v = 1.0;
+    for (auto &v : s1) v = 1.0;
+    for (auto &v : q) v = 1.0;
+    std::vector<DiagEntry> thr, slot[kMaxRegBits];
+    auto entry = [](int a, int c, cd f0, cd f1) {
+        DiagEntry e{};
+        e.a = a;
+        e.c = c;
+        e.f0[0] = f0.real(), e.f0[1] = f0.imag();
+        e.f1[0] = f1.real(), e.f1[1] = f1.imag();
+        return e;
+    };
+    for (int ii : run) {
+        const Item &it = items[ii];
+        if (it.kind == OP_DIAG1) {
+            const cd p0(it.m[0], it.m[1]), p1(it.m[2], it.m[3]);
+            const int j = slot_of(it.qa);
+            if (j >= 0) {
+                s0[j] *= p0;
+                s1[j] *= p1;
+            } else {
+                thr.push_back(entry(ref(it.qa), kNoRef, p0, p1));
+            }
+        } else {
+            const cd phi(it.m[0], it.m[1]);
+            const int ja = slot_of(it.qa), jc = slot_of(it.qc);
+            if (ja >= 0 && jc >= 0) {
+                const int lo = std::min(ja, jc), hi = std::max(ja, jc);
+                q[hi * (hi - 1) / 2 + lo] *= phi;
+            } else if (ja >= 0) {
+                slot[ja].push_back(entry(ref(it.qc), kNoRef, 1.0, phi));
+            } else if (jc >= 0) {
+                slot[jc].push_back(entry(ref(it.qa), kNoRef, 1.0, phi));
+            } else {
+                thr.push_back(entry(ref(it.qa), ref(it.qc), 1.0, phi));
+            }
+        }
+    }
+    DiagRun d{};
+    cd c0 = 1.0;
+    for (int j = 0; j < rb; ++j) c0 *= s0[j];
+    d.c0[0] = c0.real(), d.c0[1] = c0.imag();
+    for (int j = 0; j < kMaxRegBits; ++j) {
+        // every factor has modulus 1, so s1 / s0 = s1 conj(s0)
+        const cd r = s1[j] * std::conj(s0[j]);
+        d.r[j][0] = r.real(), d.r[j][1] = r.imag();
+    }
+    for (int k = 0; k < kMaxRegBits * (kMaxRegBits - 1) / 2; ++k) d.q[k][0] = q[k].real(), d.q[k][1] = q[k].imag();
+    d.e_begin = (int)prog->entries.size();
+    prog->entries.insert(prog->entries.end(), thr.begin(), thr.end());
+    for (int j = 0; j <= kMaxRegBits; ++j) {
+        d.s_begin[j] = (int)prog->entries.size();
+        if (j < rb) prog->entries.insert(prog->entries.end(), slot[j].begin(), slot[j].end());
+    }
+    prog->runs.push_back(d);
+}
+
 Program build_program(const std::vector<Gate> &gates, const std::vector<PassRange> &ranges,
                       const PlanConfig &cfg) {
     Program prog;
@@ -664,7 +730,24 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
                 auto f = std::find(S.begin(), S.end(), pos_of[qq]);
                 return f == S.end() ? -1 : (int)(f - S.begin());
             };
-            for (int ii : pp.items) {
+            auto is_diag = [&](int ii) { return items[ii].kind == OP_DIAG1 || items[ii].kind == OP_DIAG2; };
+            for (size_t x = 0; x < pp.items.size(); ++x) {
+                const int ii = pp.items[x];
+                if (cfg.diag_run_min > 0 && !cfg.reverse && is_diag(ii)) {
+                    size_t y = x;
+                    while (y < pp.items.size() && is_diag(pp.items[y])) ++y;
+                    if ((int)(y - x) >= cfg.diag_run_min) {
+                        DevOp op{};
+                        op.kind = OP_DIAGRUN;
+                        op.g = -1;
+                        op.a = (int)prog.runs.size();
+                        std::vector<int> run(pp.items.begin() + x, pp.items.begin() + y);
+                        append_diag_run(items, run, rb, slot_of, ref, &prog);
+                        prog.ops.push_back(op);
+                        x = y - 1;
+                        continue;
+                    }
+                }
                 const Item &it = items[ii];
                 const int q = needs_register(it);
                 const int slot = q >= 0 ? slot_of(q) : -1;
@@ -923,7 +1006,17 @@ void append_program(Program *dst, const Program &src) {
         ph.op_end += op0;
         dst->phases.push_back(ph);
     }
-    dst->ops.insert(dst->ops.end(), src.ops.begin(), src.ops.end());
+    const int r0 = (int)dst->runs.size(), e0 = (int)dst->entries.size();
+    for (DevOp op : src.ops) {
+        if (op.kind == OP_DIAGRUN) op.a += r0;
+        dst->ops.push_back(op);
+    }
+    for (DiagRun d : src.runs) {
+        d.e_begin += e0;
+        for (int &b : d.s_begin) b += e0;
+        dst->runs.push_back(d);
+    }
+    dst->entries.insert(dst->entries.end(), src.entries.begin(), src.entries.end());
     (void)pass0;
 }
 

@@ -33,6 +33,7 @@ struct PlanConfig {
     int max_gates_per_pass = 4096;
     int dense_min_gates = 1 << 30;  // a pass on <= 6 qubits with this many gates runs as a dense block
     bool use_classes = true;        // single-gate passes take their tile shape from the class table
+    int diag_run_min = 3;           // consecutive diagonal ops fused into one (0: never)
 };
 
 // Pass classes for tuning: by the highest qubit a pass needs in registers.
@@ -55,6 +56,7 @@ struct Tuning {
     int nt = 1;
     int swz_bits = 4;
     int xcd = 1;
+    int diag_run_min = 3;  // fuse runs of at least this many diagonal ops (0: never)
     int pipe = 0;          // persistent prefetching blocks: 0 never, 1 heavy passes, 2 always
     int pipe_min_ops = 4;  // a pass is heavy with several phases or at least this many ops
     int dense_min_gates = 1 << 30;
@@ -87,6 +89,8 @@ struct Program {
     int64_t max_grad_part = 0;       // adjoint: largest per-pass partial-sum block (doubles)
     std::vector<DenseDesc> dense;    // dense steps (passes flagged PASS_DENSE)
     std::vector<double> dense_ut;    // their transposed matrices: re block then im block, 4^k each
+    std::vector<DiagRun> runs;       // fused diagonal runs (OP_DIAGRUN ops)
+    std::vector<DiagEntry> entries;  // their per-thread factors
 };
 
 // Validates a circuit (qubits in range, q0 != q1, known code, finite params,

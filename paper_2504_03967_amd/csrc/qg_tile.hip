@@ -15,9 +15,9 @@ using namespace dev;
 
 template <typename R, int RB, int NS>
 __device__ __forceinline__ void tile_pass(const PassDesc &P, const PhaseDesc *__restrict__ phases,
-                                          const DevOp *__restrict__ ops, typename V2<R>::T *__restrict__ psi,
-                                          typename V2<R>::T *__restrict__ lam, double *__restrict__ gpart,
-                                          int64_t gstride) {
+                                          const DevOp *__restrict__ ops, const DiagTables &dt,
+                                          typename V2<R>::T *__restrict__ psi, typename V2<R>::T *__restrict__ lam,
+                                          double *__restrict__ gpart, int64_t gstride) {
     using C = typename V2<R>::T;
     extern __shared__ __align__(16) unsigned char smem[];
     C *lds = reinterpret_cast<C *>(smem);
@@ -26,7 +26,7 @@ __device__ __forceinline__ void tile_pass(const PassDesc &P, const PhaseDesc *__
     C *const st[2] = {psi, lam};
     C a[NS][1 << RB];
     tile_load<R, RB, NS>(P, phases[0], gbase, st, a, tid);
-    tile_phases<R, RB, NS>(P, phases, ops, gbase, a, lds, gpart, gstride, blockIdx.x, tid, true);
+    tile_phases<R, RB, NS>(P, phases, ops, dt, gbase, a, lds, gpart, gstride, blockIdx.x, tid, true);
     tile_store<R, RB, NS>(P, phases[P.n_phase - 1], gbase, st, a, tid);
 }
 
@@ -37,7 +37,8 @@ __device__ __forceinline__ void tile_pass(const PassDesc &P, const PhaseDesc *__
 // of the tiles; the host launches a multiple of 8 blocks, at most n_tiles.
 template <typename R, int RB>
 __device__ __forceinline__ void tile_pass_pipe(const PassDesc &P, const PhaseDesc *__restrict__ phases,
-                                               const DevOp *__restrict__ ops, typename V2<R>::T *__restrict__ psi) {
+                                               const DevOp *__restrict__ ops, const DiagTables &dt,
+                                               typename V2<R>::T *__restrict__ psi) {
     using C = typename V2<R>::T;
     constexpr int NR = 1 << RB;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -65,7 +66,7 @@ __device__ __forceinline__ void tile_pass_pipe(const PassDesc &P, const PhaseDes
         const bool more = wn < end;
         if (more) tile_load<R, RB, 1>(P, first, tile_deposit(P, wn), st, nx, tid);
         const uint64_t gbase = tile_deposit(P, w);
-        tile_phases<R, RB, 1>(P, phases, ops, gbase, a, lds, nullptr, 0, w, tid, true);
+        tile_phases<R, RB, 1>(P, phases, ops, dt, gbase, a, lds, nullptr, 0, w, tid, true);
         tile_store<R, RB, 1>(P, last, gbase, st, a, tid);
         if (!more) break;
 #pragma unroll
@@ -76,33 +77,37 @@ __device__ __forceinline__ void tile_pass_pipe(const PassDesc &P, const PhaseDes
 
 template <typename R, int RB>
 __global__ void __launch_bounds__(256)
-k_tile_pipe(const unsigned char *__restrict__ dev, uint32_t pass_off, uint32_t phase_off, uint32_t op_off,
-            int pass_idx, typename V2<R>::T *__restrict__ psi) {
-    const PassDesc &P = reinterpret_cast<const PassDesc *>(dev + pass_off)[pass_idx];
-    tile_pass_pipe<R, RB>(P, reinterpret_cast<const PhaseDesc *>(dev + phase_off) + P.phase_begin,
-                          reinterpret_cast<const DevOp *>(dev + op_off), psi);
+k_tile_pipe(const unsigned char *__restrict__ dev, const ProgOffsets offs, int pass_idx,
+            typename V2<R>::T *__restrict__ psi) {
+    const PassDesc &P = reinterpret_cast<const PassDesc *>(dev + offs.pass)[pass_idx];
+    const DiagTables dt{reinterpret_cast<const DiagRun *>(dev + offs.run),
+                        reinterpret_cast<const DiagEntry *>(dev + offs.entry)};
+    tile_pass_pipe<R, RB>(P, reinterpret_cast<const PhaseDesc *>(dev + offs.phase) + P.phase_begin,
+                          reinterpret_cast<const DevOp *>(dev + offs.op), dt, psi);
 }
 
 template <typename R, int RB>
 __global__ void __launch_bounds__(256) k_tile_inl_pipe(const InlineProg prog, typename V2<R>::T *__restrict__ psi) {
-    tile_pass_pipe<R, RB>(prog.pass, prog.phases, prog.ops, psi);
+    tile_pass_pipe<R, RB>(prog.pass, prog.phases, prog.ops, DiagTables{nullptr, nullptr}, psi);
 }
 
 template <typename R, int RB, int NS>
 __global__ void __launch_bounds__(256)
-k_tile(const unsigned char *__restrict__ dev, uint32_t pass_off, uint32_t phase_off, uint32_t op_off,
-       int pass_idx, typename V2<R>::T *__restrict__ psi, typename V2<R>::T *__restrict__ lam,
-       double *__restrict__ gpart, int64_t gstride) {
-    const PassDesc &P = reinterpret_cast<const PassDesc *>(dev + pass_off)[pass_idx];
-    tile_pass<R, RB, NS>(P, reinterpret_cast<const PhaseDesc *>(dev + phase_off) + P.phase_begin,
-                         reinterpret_cast<const DevOp *>(dev + op_off), psi, lam, gpart, gstride);
+k_tile(const unsigned char *__restrict__ dev, const ProgOffsets offs, int pass_idx,
+       typename V2<R>::T *__restrict__ psi, typename V2<R>::T *__restrict__ lam, double *__restrict__ gpart,
+       int64_t gstride) {
+    const PassDesc &P = reinterpret_cast<const PassDesc *>(dev + offs.pass)[pass_idx];
+    const DiagTables dt{reinterpret_cast<const DiagRun *>(dev + offs.run),
+                        reinterpret_cast<const DiagEntry *>(dev + offs.entry)};
+    tile_pass<R, RB, NS>(P, reinterpret_cast<const PhaseDesc *>(dev + offs.phase) + P.phase_begin,
+                         reinterpret_cast<const DevOp *>(dev + offs.op), dt, psi, lam, gpart, gstride);
 }
 
 template <typename R, int RB, int NS>
 __global__ void __launch_bounds__(256)
 k_tile_inl(const InlineProg prog, typename V2<R>::T *__restrict__ psi, typename V2<R>::T *__restrict__ lam,
            double *__restrict__ gpart, int64_t gstride) {
-    tile_pass<R, RB, NS>(prog.pass, prog.phases, prog.ops, psi, lam, gpart, gstride);
+    tile_pass<R, RB, NS>(prog.pass, prog.phases, prog.ops, DiagTables{nullptr, nullptr}, psi, lam, gpart, gstride);
 }
 
 // Resident blocks per CU of a kernel at a block size and dynamic LDS size,
@@ -130,9 +135,8 @@ int resident_blocks(const void *fn, int threads, size_t lds) {
 }
 
 template <typename R, int RB, int NS>
-hipError_t launch_one(const PassDesc &hp, const InlineProg *inl, const void *dev, size_t pass_off,
-                      size_t phase_off, size_t op_off, int pass_idx, void *psi, void *lam, double *gpart,
-                      int64_t gstride, hipStream_t st) {
+hipError_t launch_one(const PassDesc &hp, const InlineProg *inl, const void *dev, const ProgOffsets &offs,
+                      int pass_idx, void *psi, void *lam, double *gpart, int64_t gstride, hipStream_t st) {
     using C = typename V2<R>::T;
     const size_t lds = hp.n_phase > 1 ? (size_t(1) << hp.b) * sizeof(C) : 0;
     const bool pipe = NS == 1 && (hp.flags & PASS_PIPE);
@@ -164,8 +168,7 @@ hipError_t launch_one(const PassDesc &hp, const InlineProg *inl, const void *dev
                                static_cast<C *>(psi));
         } else {
             hipLaunchKernelGGL((k_tile_pipe<R, RB>), dim3((uint32_t)g), block, lds, st,
-                               static_cast<const unsigned char *>(dev), (uint32_t)pass_off, (uint32_t)phase_off,
-                               (uint32_t)op_off, pass_idx, static_cast<C *>(psi));
+                               static_cast<const unsigned char *>(dev), offs, pass_idx, static_cast<C *>(psi));
         }
         return hipGetLastError();
     }
@@ -174,39 +177,37 @@ hipError_t launch_one(const PassDesc &hp, const InlineProg *inl, const void *dev
         hipLaunchKernelGGL((k_tile_inl<R, RB, NS>), grid, block, lds, st, *inl, static_cast<C *>(psi),
                            static_cast<C *>(lam), gpart, gstride);
     } else {
-        hipLaunchKernelGGL((k_tile<R, RB, NS>), grid, block, lds, st, static_cast<const unsigned char *>(dev),
-                           (uint32_t)pass_off, (uint32_t)phase_off, (uint32_t)op_off, pass_idx,
-                           static_cast<C *>(psi), static_cast<C *>(lam), gpart, gstride);
+        hipLaunchKernelGGL((k_tile<R, RB, NS>), grid, block, lds, st, static_cast<const unsigned char *>(dev), offs,
+                           pass_idx, static_cast<C *>(psi), static_cast<C *>(lam), gpart, gstride);
     }
     return hipGetLastError();
 }
 
 template <typename R, int NS>
-hipError_t launch_rb(const PassDesc &hp, const InlineProg *inl, const void *dev, size_t a, size_t b, size_t c,
-                     int pi, void *psi, void *lam, double *gp, int64_t gs, hipStream_t st) {
+hipError_t launch_rb(const PassDesc &hp, const InlineProg *inl, const void *dev, const ProgOffsets &o, int pi,
+                     void *psi, void *lam, double *gp, int64_t gs, hipStream_t st) {
     switch (hp.rb) {
-    case 1: return launch_one<R, 1, NS>(hp, inl, dev, a, b, c, pi, psi, lam, gp, gs, st);
-    case 2: return launch_one<R, 2, NS>(hp, inl, dev, a, b, c, pi, psi, lam, gp, gs, st);
-    case 3: return launch_one<R, 3, NS>(hp, inl, dev, a, b, c, pi, psi, lam, gp, gs, st);
-    case 4: return launch_one<R, 4, NS>(hp, inl, dev, a, b, c, pi, psi, lam, gp, gs, st);
-    case 5: return launch_one<R, 5, NS>(hp, inl, dev, a, b, c, pi, psi, lam, gp, gs, st);
+    case 1: return launch_one<R, 1, NS>(hp, inl, dev, o, pi, psi, lam, gp, gs, st);
+    case 2: return launch_one<R, 2, NS>(hp, inl, dev, o, pi, psi, lam, gp, gs, st);
+    case 3: return launch_one<R, 3, NS>(hp, inl, dev, o, pi, psi, lam, gp, gs, st);
+    case 4: return launch_one<R, 4, NS>(hp, inl, dev, o, pi, psi, lam, gp, gs, st);
+    case 5: return launch_one<R, 5, NS>(hp, inl, dev, o, pi, psi, lam, gp, gs, st);
     }
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_tile(bool c64, const PassDesc &hp, const InlineProg *inl, const void *dev, size_t pass_off,
-                       size_t phase_off, size_t op_off, int pass_idx, int ns, void *psi, void *lam, double *gpart,
-                       int64_t gstride, hipStream_t st) {
+hipError_t launch_tile(bool c64, const PassDesc &hp, const InlineProg *inl, const void *dev, const ProgOffsets &offs,
+                       int pass_idx, int ns, void *psi, void *lam, double *gpart, int64_t gstride, hipStream_t st) {
     if (hp.n_tiles == 0 || hp.n_tiles > 0x7fffffffull || hp.tb > kMaxThreadBits || hp.n_phase < 1)
         return hipErrorInvalidValue;
     if (ns == 2) {
-        return c64 ? launch_rb<float, 2>(hp, inl, dev, pass_off, phase_off, op_off, pass_idx, psi, lam, gpart, gstride, st)
-                   : launch_rb<double, 2>(hp, inl, dev, pass_off, phase_off, op_off, pass_idx, psi, lam, gpart, gstride, st);
+        return c64 ? launch_rb<float, 2>(hp, inl, dev, offs, pass_idx, psi, lam, gpart, gstride, st)
+                   : launch_rb<double, 2>(hp, inl, dev, offs, pass_idx, psi, lam, gpart, gstride, st);
     }
-    return c64 ? launch_rb<float, 1>(hp, inl, dev, pass_off, phase_off, op_off, pass_idx, psi, nullptr, nullptr, 0, st)
-               : launch_rb<double, 1>(hp, inl, dev, pass_off, phase_off, op_off, pass_idx, psi, nullptr, nullptr, 0, st);
+    return c64 ? launch_rb<float, 1>(hp, inl, dev, offs, pass_idx, psi, nullptr, nullptr, 0, st)
+               : launch_rb<double, 1>(hp, inl, dev, offs, pass_idx, psi, nullptr, nullptr, 0, st);
 }
 
 }  // namespace qg

@@ -95,6 +95,28 @@ __device__ __forceinline__ Bit make_bit(int ref, uint64_t gbase) {
     return b;
 }
 
+// The fused diagonal runs of the running program (null where a program has none).
+struct DiagTables {
+    const DiagRun *runs;
+    const DiagEntry *entries;
+};
+
+// Condition of a diagonal-run entry for this thread (refs are thread bits or
+// qubits outside the tile).
+__device__ __forceinline__ bool entry_on(const DiagEntry &x, uint64_t gbase, uint32_t tp) {
+    bool on = make_bit(x.a, gbase).of(tp);
+    if (x.c != kNoRef) on = on && make_bit(x.c, gbase).of(tp);
+    return on;
+}
+
+// (r, i) *= (on ? f1 : f0), in FP64.
+__device__ __forceinline__ void cmul_acc(double &r, double &i, bool on, const double (&f0)[2], const double (&f1)[2]) {
+    const double fr = on ? f1[0] : f0[0], fi = on ? f1[1] : f0[1];
+    const double nr = r * fr - i * fi;
+    i = r * fi + i * fr;
+    r = nr;
+}
+
 // Component-wise select (a select of whole 16-byte vectors can become a select
 // of their addresses, which forces the register arrays into scratch memory).
 template <typename C>
@@ -416,7 +438,7 @@ __device__ __forceinline__ double tile_obs_terms(const PassDesc &P, const PhaseD
 // (o may be a); gradient ops (adjoint sweeps) also write their per-wave
 // partial sum and copy a to o.
 template <typename R, int RB, int NS>
-__device__ __forceinline__ void apply_op(const DevOp &op, const typename V2<R>::T (&a)[NS][1 << RB],
+__device__ __forceinline__ void apply_op(const DevOp &op, const DiagTables &dt, const typename V2<R>::T (&a)[NS][1 << RB],
                                          typename V2<R>::T (&o)[NS][1 << RB], uint64_t gbase, uint32_t tp,
                                          const uint32_t (&ep)[1 << RB], double *__restrict__ gpart,
                                          int64_t gstride, uint64_t tile_idx, int tid) {
@@ -447,6 +469,49 @@ __device__ __forceinline__ void apply_op(const DevOp &op, const typename V2<R>::
         const bool on = make_bit(op.c, gbase).of(tp);
         const R re = on ? m[0] : (R)1, im = on ? m[1] : (R)0;
         QG_SLOT_SWITCH(op.a, (apply_slot_factor<J_>(a, o, re, im)));
+    } else if (kind == OP_DIAGRUN) {
+        // Factor of element e: tf * prod_{slot j of e} r_j * prod_{slots j<k of e} q_jk,
+        // built in FP64 from the element without its top slot bit.
+        const DiagRun &d = dt.runs[op.a];
+        double tr = d.c0[0], ti = d.c0[1];
+        for (int k = d.e_begin; k < d.s_begin[0]; ++k) {
+            const DiagEntry &x = dt.entries[k];
+            cmul_acc(tr, ti, entry_on(x, gbase, tp), x.f0, x.f1);
+        }
+        double rr[RB], ri[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            rr[j] = d.r[j][0];
+            ri[j] = d.r[j][1];
+            for (int k = d.s_begin[j]; k < d.s_begin[j + 1]; ++k) {
+                const DiagEntry &x = dt.entries[k];
+                cmul_acc(rr[j], ri[j], entry_on(x, gbase, tp), x.f0, x.f1);
+            }
+        }
+        double fr[NR], fi[NR];
+        fr[0] = tr;
+        fi[0] = ti;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) o[s][0] = cmul(a[s][0], (R)tr, (R)ti);
+#pragma unroll
+        for (int e = 1; e < NR; ++e) {
+            const int j = 31 - __builtin_clz((unsigned)e);
+            const int e0 = e ^ (1 << j);
+            double xr = fr[e0] * rr[j] - fi[e0] * ri[j], xi = fr[e0] * ri[j] + fi[e0] * rr[j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) {
+                if (!((e0 >> k) & 1)) continue;
+                const double qr = d.q[j * (j - 1) / 2 + k][0], qi = d.q[j * (j - 1) / 2 + k][1];
+                const double nr = xr * qr - xi * qi;
+                xi = xr * qi + xi * qr;
+                xr = nr;
+            }
+            fr[e] = xr;
+            fi[e] = xi;
+            // applied at once, so that only the factors still needed as parents stay live
+#pragma unroll
+            for (int s = 0; s < NS; ++s) o[s][e] = cmul(a[s][e], (R)xr, (R)xi);
+        }
     } else if (kind == OP_DIAG1) {
         // thread bit or outside the tile: one factor per thread
         const bool one = make_bit(op.a, gbase).of(tp);
@@ -503,7 +568,7 @@ __device__ __forceinline__ void apply_op(const DevOp &op, const typename V2<R>::
 // then the phase's ops.  `active` is false for threads beyond the tile's 2^tb.
 template <typename R, int RB, int NS>
 __device__ __forceinline__ void tile_phases(const PassDesc &P, const PhaseDesc *__restrict__ phases,
-                                            const DevOp *__restrict__ ops, uint64_t gbase,
+                                            const DevOp *__restrict__ ops, const DiagTables &dt, uint64_t gbase,
                                             typename V2<R>::T (&a)[NS][1 << RB], typename V2<R>::T *lds,
                                             double *__restrict__ gpart, int64_t gstride, uint64_t tile_idx,
                                             int tid, bool active) {
@@ -552,10 +617,10 @@ __device__ __forceinline__ void tile_phases(const PassDesc &P, const PhaseDesc *
         C b[NS][NR];
         int i = ph.op_begin;
         for (; i + 1 < ph.op_end; i += 2) {
-            apply_op<R, RB, NS>(ops[i], a, b, gbase, tp, ep, gpart, gstride, tile_idx, tid);
-            apply_op<R, RB, NS>(ops[i + 1], b, a, gbase, tp, ep, gpart, gstride, tile_idx, tid);
+            apply_op<R, RB, NS>(ops[i], dt, a, b, gbase, tp, ep, gpart, gstride, tile_idx, tid);
+            apply_op<R, RB, NS>(ops[i + 1], dt, b, a, gbase, tp, ep, gpart, gstride, tile_idx, tid);
         }
-        if (i < ph.op_end) apply_op<R, RB, NS>(ops[i], a, a, gbase, tp, ep, gpart, gstride, tile_idx, tid);
+        if (i < ph.op_end) apply_op<R, RB, NS>(ops[i], dt, a, a, gbase, tp, ep, gpart, gstride, tile_idx, tid);
     }
 }
 

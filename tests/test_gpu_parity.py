@@ -278,3 +278,47 @@ def test_persistent_prefetching_blocks_complex64(qg):
         qg.set_tuning("pipe", saved)
     assert np.array_equal(out[0], out[1])
     assert abs(np.sum(np.abs(out[0].astype(np.complex128)) ** 2) - 1) < 1e-4
+
+
+def diagonal_heavy_circuit(n, seed, blocks=12):
+    """Layers of U3 separated by long runs of CP / CZ / RZ on random qubits, so that passes
+    hold diagonal runs whose qubits are register slots, thread bits and qubits outside the
+    tile, in every combination."""
+    rng = W.SplitMix64(seed)
+    b = W.CircuitBuilder(n)
+    for _ in range(blocks):
+        for q in range(n):
+            b.g1(W.U3, q, *(2 * math.pi * rng.uniform(3)))
+        for _ in range(3 * n):
+            op = (W.CP, W.CZ, W.RZ)[int(rng.below(3)[0])]
+            q1 = int(rng.below(n)[0])
+            if op == W.RZ:
+                b.g1(W.RZ, q1, float(2 * math.pi * rng.uniform(1)[0]))
+                continue
+            q0 = int(rng.below(n)[0])
+            while q0 == q1:
+                q0 = int(rng.below(n)[0])
+            b.add(op, q0, q1, [float(2 * math.pi * rng.uniform(1)[0]), 0.0, 0.0])
+    return b.build()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [9, 14, 17])
+def test_fused_diagonal_runs_match_oracle(qg, n, dtype):
+    """Runs of diagonal gates fused into one factor per amplitude (tables built on the host,
+    per-thread entries on the device) against the oracle, and against unfused runs."""
+    circ = W.concat(diagonal_heavy_circuit(n, 100 + n), W.qft(n).build())
+    ref = oracle.simulate(circ)
+    saved = qg.get_tuning("diag_run_min")
+    out = []
+    try:
+        for m in (3, 0):
+            qg.set_tuning("diag_run_min", m)
+            for fusion in (0, 1):
+                st = run(qg, circ, dtype, fusion)
+                out.append(host(st))
+                st.close()
+    finally:
+        qg.set_tuning("diag_run_min", saved)
+    for o in out:
+        assert np.max(np.abs(o - ref)) < TOL[dtype]
