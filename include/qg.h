@@ -267,9 +267,10 @@ qg_status qg_get_tuning(const char *key, int64_t *value);
 /* Autotuner (a measured search; not part of the paper).  Passes are classed by
  * the highest qubit they need in registers: 0 below the cache-line bits, 1 below
  * 12, 2 below 20, 3 from 20 up, 4 none (diagonal only).  For each class that the
- * state's qubit count can exercise, single-gate passes are timed (HIP events,
- * median of reps after one warm-up run) on the state for 8 candidate
- * (tile bits, register bits, swizzle) shapes; the fastest becomes the class's
+ * state's qubit count can exercise, single-gate passes on up to three of the
+ * class's targets are timed (HIP events, median of reps after one warm-up run,
+ * summed over the targets) on the state for 8 candidate (tile bits, register
+ * bits, swizzle) shapes; the fastest becomes the class's
  * entry for the state's dtype (tuning keys cls<k>_tile_<dt>, cls<k>_reg_<dt>,
  * cls<k>_swz_<dt>; fused passes use the class's swizzle).  The state's
  * amplitudes are overwritten and reset to |0...0> at the end; the call waits
