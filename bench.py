@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="omit the adjoint / batched speed-ups and the learned-fusion gain")
     ap.add_argument("--cm-samples", type=int, default=1500, help="timed passes for the cost-model dataset")
+    ap.add_argument("--config3-only", type=int, default=0, metavar="N",
+                    help="only time config 3 on N qubits (c128) and print its JSON line (profiling)")
     return ap.parse_args()
 
 
@@ -72,20 +74,49 @@ def timed(fn, sync):
     return time.perf_counter() - t0, r
 
 
-def config3_timing(qg, W, torch):
-    """The paper-shaped large circuit: 100 random U3 + CX layers and a QFT on 31 qubits
-    (complex128, 32 GiB state), greedy (commutation-aware) fusion."""
-    circ = W.config3(31)
-    st = qg.State(31, "c128")
+FP64_PEAK_TFLOPS = 78.6  # MI355X vector (and matrix) FP64
+
+
+def algorithmic_flops_per_index(circ, W) -> float:
+    """Floating-point operations per amplitude index of a circuit, counting what the gate
+    requires (a fused multiply-add is 2): a general 2x2 complex gate 14 per amplitude (two
+    complex products and a complex sum), a real or RX-form matrix 6 (two real-by-complex
+    products and a sum), RZ 6 (one complex product), CP / CZ 1.5 (one complex product on a
+    quarter of the amplitudes), CX / SWAP / X 0 (data movement only)."""
+    ops = circ.gate_type[:, 0]
+    per = {W.U3: 14.0, W.H: 6.0, W.RY: 6.0, W.RX: 6.0, W.RZ: 6.0, W.CP: 1.5, W.CZ: 1.5}
+    return float(sum(per.get(int(o), 0.0) for o in ops))
+
+
+def config3_timing(qg, W, torch, n: int = 31):
+    """The paper-shaped large circuit: 100 random U3 + CX layers and a QFT on n qubits
+    (complex128; 32 GiB at 31 qubits), greedy (commutation-aware) fusion.  Its fused passes
+    hold ~20 gates each, so they are bound by FP64 issue and register-layout exchanges
+    rather than HBM: both rooflines are reported."""
+    circ = W.config3(n)
+    st = qg.State(n, "c128")
     _, npass = qg.plan_passes(circ, "c128", qg.FUSE_GREEDY)
     st.apply(circ, qg.FUSE_GREEDY)  # warm-up (plans, code)
     st.reset()
-    t, _ = timed(lambda: st.apply(circ, qg.FUSE_GREEDY), torch.cuda.synchronize)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    st.apply(circ, qg.FUSE_GREEDY)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3
     st.close()
     torch.cuda.empty_cache()
-    return {"workload": "31 qubits c128: 100 layers (U3 on every qubit, 15 low/high CX) + QFT(31), 5111 gates",
-            "passes": npass, "t_s": round(t, 3), "amp_updates_per_s": circ.n_gates * (1 << 31) / t,
-            "full_pass_equivalent_GBps": round(npass * 2 * (1 << 31) * 16 / t / 1e9, 1)}
+    flops = algorithmic_flops_per_index(circ, W) * (1 << n)
+    hbm = npass * 2 * (1 << n) * 16
+    return {"workload": f"{n} qubits c128: 100 layers (U3 on every qubit, {n // 2} low/high CX) + QFT({n}), "
+                        f"{circ.n_gates} gates",
+            "passes": npass, "t_s": round(t, 3), "amp_updates_per_s": circ.n_gates * (1 << n) / t,
+            "fp64_TFLOPs": round(flops / t / 1e12, 2),
+            "fp64_frac": round(flops / t / 1e12 / FP64_PEAK_TFLOPS, 4),
+            "full_pass_equivalent_GBps": round(hbm / t / 1e9, 1),
+            "hbm_frac": round(hbm / t / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def adjoint_speedup(qg, W, torch):
@@ -200,6 +231,9 @@ def main():
     from paper_2504_03967_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.config3_only:
+        print(json.dumps({"config3": config3_timing(qg, W, torch, args.config3_only)}), flush=True)
+        return
     n = args.n
     amp_bytes = 16 if args.dtype == "c128" else 8
     from paper_2504_03967_amd import autotune

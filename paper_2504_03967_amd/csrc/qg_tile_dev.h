@@ -272,22 +272,8 @@ __device__ __forceinline__ double grad_xy(const C (&a)[NS][NR], bool isy) {
 }
 
 
-// Global index bits of logical tile w: deposit w into the free runs (after
-// the optional swizzle).
-// Calls the slot-J form of an op for the runtime slot `slot` < NR's bit count:
-// the last slot is the fall-through, so that no path leaves the registers
-// untouched (an untouched path makes the compiler copy the whole register
-// array around every op).
-template <int J, int RB, int NS, typename C, typename R>
-__device__ __forceinline__ void dispatch_mat(int slot, C (&a)[NS][1 << RB], const R (&m)[8]) {
-    if constexpr (J == RB - 1) {
-        apply_mat<J>(a, m);
-    } else {
-        if (slot == J) apply_mat<J>(a, m);
-        else dispatch_mat<J + 1, RB>(slot, a, m);
-    }
-}
-
+// Adjoint partial of the X or Y generator on the runtime register slot
+// `slot` (< RB); the last slot is the fall-through.
 template <int J, int RB, int NS, typename C>
 __device__ __forceinline__ double dispatch_grad_xy(int slot, const C (&a)[NS][1 << RB], bool isy) {
     if constexpr (J == RB - 1) {
@@ -297,6 +283,8 @@ __device__ __forceinline__ double dispatch_grad_xy(int slot, const C (&a)[NS][1 
     }
 }
 
+// Global index bits of logical tile w: deposit w into the free runs (after
+// the optional swizzle).
 __device__ __forceinline__ uint64_t tile_deposit(const PassDesc &P, uint64_t w) {
     uint64_t gbase = P.fixed_val;
     if (P.swz_bits > 0) {
