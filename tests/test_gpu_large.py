@@ -1,12 +1,14 @@
-"""Full-size checks where the oracle cannot run (32 GiB and 128 GiB states): properties
-that hold at any size — norm conservation, mirror circuits, the QFT closed form on
-basis states, GHZ, Porter-Thomas statistics of random circuits and of their shots."""
+"""Full-size checks where the oracle cannot hold the state (16 to 128 GiB): properties that
+hold at any size — norm conservation, mirror circuits, the QFT closed form on basis states,
+GHZ, Porter-Thomas statistics of random circuits and of their shots — and the benchmark's
+own sweep on sampled amplitudes the oracle computes from a factorised state."""
 import math
 
 import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_2504_03967_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -94,3 +96,59 @@ def test_ghz_at_maximum_size(qg, n, dtype):
     assert abs(t[0] - 1) < tol and abs(t[1]) < tol
     st.close()
     del st
+
+
+def factorised_reference(circ):
+    """Amplitude function of a circuit whose two-qubit gates all act inside one small qubit set E:
+    the state is (state of E) x (one single-qubit state per other qubit), each part computed by
+    the oracle on its own qubits, in the circuit's gate order."""
+    n = circ.n_qubits
+    E = sorted({int(q) for op, q0, q1 in circ.gate_type if op in W.TWO_QUBIT for q in (q0, q1)})
+    pos = {q: k for k, q in enumerate(E)}
+    eb = W.CircuitBuilder(len(E))
+    singles = {q: W.CircuitBuilder(1) for q in range(n) if q not in pos}
+    for (op, q0, q1), p in zip(circ.gate_type, circ.gate_param):
+        if op in W.TWO_QUBIT:
+            eb.add(op, pos[int(q0)], pos[int(q1)], p)
+        elif int(q1) in pos:
+            eb.add(op, -1, pos[int(q1)], p)
+        else:
+            singles[int(q1)].add(op, -1, 0, p)
+    psi_e = oracle.simulate(eb.build())
+    phi = {q: oracle.simulate(b.build()) for q, b in singles.items()}
+
+    def amp(i):
+        e = sum(((i >> q) & 1) << k for k, q in enumerate(E))
+        v = psi_e[e]
+        for q, f in phi.items():
+            v *= f[(i >> q) & 1]
+        return v
+    return amp
+
+
+@pytest.mark.parametrize("n,dtype", [(30, "c128"), (31, "c64")])
+def test_bench_sweep_at_full_size_sampled_amplitudes(qg, n, dtype, tmp_path, monkeypatch):
+    """The benchmark's own workload at its full size and launch configuration (autotuned tile
+    shapes, the same fusion modes per part): the U3 layer, then the 65-gate sweep, checked on
+    4096 sampled amplitudes against the oracle's factorised state (its CX / CP / SWAP pairs
+    share six qubits, everything else is single-qubit)."""
+    from paper_2504_03967_amd import autotune
+    monkeypatch.setenv("QG_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    before = autotune.current(dtype)
+    try:
+        autotune.tuned(n, dtype)
+        prep, full, parts = W.sweep(n)
+        st = qg.State(n, dtype)
+        st.apply(prep, qg.FUSE_NONE)
+        for name, circ in parts:
+            st.apply(circ, qg.FUSE_GREEDY if name.startswith("fused") else qg.FUSE_NONE)
+        amp = factorised_reference(W.concat(prep, full))
+        idx = np.concatenate([np.arange(16), W.config3_indices(n, seed=11, count=4080)]).astype(np.int64)
+        got = st.tensor[torch.as_tensor(idx, device="cuda")].cpu().numpy().astype(np.complex128)
+        want = np.array([amp(int(i)) for i in idx])
+        assert np.max(np.abs(got - want)) < TOL[dtype]
+        terms, _ = st.expval([0])
+        assert abs(terms.cpu().numpy()[0] - 1) < TOL[dtype]
+        st.close()
+    finally:
+        autotune.apply(before, dtype)
