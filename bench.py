@@ -119,6 +119,31 @@ def config3_timing(qg, W, torch, n: int = 31):
             "hbm_frac": round(hbm / t / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def paper_shaped(qg, W, torch, n: int = 30):
+    """The paper's other benchmark circuit shapes at n qubits (complex128, greedy fusion):
+    QFT(n), and random CX-block unitaries of 100 ('short') and 1000 blocks."""
+    st = qg.State(n, "c128")
+    out = {}
+    for name, circ in (("qft", W.qft(n).build()), ("cx_blocks_100", W.cx_blocks(n, 100, W.SEED_BASE + 7)),
+                       ("cx_blocks_1000", W.cx_blocks(n, 1000, W.SEED_BASE + 8))):
+        _, npass = qg.plan_passes(circ, "c128", qg.FUSE_GREEDY)
+        st.apply(circ, qg.FUSE_GREEDY)  # warm-up
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st.apply(circ, qg.FUSE_GREEDY)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3
+        out[name] = {"gates": circ.n_gates, "passes": npass, "t_ms": round(t * 1e3, 2),
+                     "amp_updates_per_s": circ.n_gates * (1 << n) / t}
+    st.close()
+    torch.cuda.empty_cache()
+    return {"n_qubits": n, **out}
+
+
 def adjoint_speedup(qg, W, torch):
     """Config 5: gradient of sum <Z_i Z_i+1> (24 qubits, 480 parameters) by one adjoint sweep
     vs the plain method, central differences (960 forward simulations + expectations)."""
@@ -357,6 +382,8 @@ def main():
     if not args.no_extras:
         log("config 3 (31 qubits c128, 5111 gates) timing")
         extras["config3"] = config3_timing(qg, W, torch)
+        log("QFT and random CX-block unitaries (30 qubits c128)")
+        extras["paper_shaped"] = paper_shaped(qg, W, torch)
         log("adjoint vs finite differences (config 5)")
         extras["adjoint"] = adjoint_speedup(qg, W, torch)
         log(f"adjoint speedup {extras['adjoint']['speedup']}x; batched vs plain loop (config 4)")

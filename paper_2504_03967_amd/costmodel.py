@@ -145,25 +145,17 @@ def mape(model: "qg.MLP", X: np.ndarray, y: np.ndarray) -> float:
 
 
 def held_out_circuits(count: int = 20, seed: int = W.SEED_BASE + 6, n_values=(20, 24, 26, 28, 30)):
-    """Random circuits in the shape of the paper's random entangling blocks (Alg. 1: two random
-    rotations then a CX on a random ordered pair) mixed with QFT tails, for plan comparisons."""
+    """Random CX-block unitaries (Alg. 1) of 30-89 blocks, every other one followed by a QFT,
+    for plan comparisons."""
     rng = W.SplitMix64(seed)
     out = []
     for c in range(count):
         n = int(n_values[c % len(n_values)])
-        b = W.CircuitBuilder(n)
         blocks = 30 + int(rng.below(60)[0])
-        for _ in range(blocks):
-            qc = int(rng.below(n)[0])
-            qt = int(rng.below(n)[0])
-            while qt == qc:
-                qt = int(rng.below(n)[0])
-            b.g1(W.RY, qc, float(2 * math.pi * rng.uniform(1)[0]))
-            b.g1(W.RZ, qt, float(2 * math.pi * rng.uniform(1)[0]))
-            b.g2(W.CX, qc, qt)
+        circ = W.cx_blocks(n, blocks, int(rng.next_u64(1)[0] % np.uint64(1 << 62)))
         if c % 2 == 0:
-            W.qft(n, b)
-        out.append(b.build())
+            circ = W.concat(circ, W.qft(n).build())
+        out.append(circ)
     return out
 
 

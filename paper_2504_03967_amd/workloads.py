@@ -158,6 +158,24 @@ def uniform_superposition(n: int) -> Circuit:
     return b.build()
 
 
+def cx_blocks(n: int, blocks: int, seed: int) -> Circuit:
+    """Random CX-block unitary (the paper's CX-block generator, Alg. 1): each block draws a
+    control q_c, then a target q_t until it differs, and applies RY(q_c), RZ(q_t) with angles
+    uniform in [0, 2 pi), then CX(q_c -> q_t).  Draw order per block: q_c, q_t (redrawn),
+    RY angle, RZ angle."""
+    rng = SplitMix64(seed)
+    b = CircuitBuilder(n)
+    for _ in range(blocks):
+        qc = int(rng.below(n)[0])
+        qt = int(rng.below(n)[0])
+        while qt == qc:
+            qt = int(rng.below(n)[0])
+        b.g1(RY, qc, float(2 * math.pi * rng.uniform(1)[0]))
+        b.g1(RZ, qt, float(2 * math.pi * rng.uniform(1)[0]))
+        b.g2(CX, qc, qt)
+    return b.build()
+
+
 def random_circuit(n: int, n_gates: int, seed: int, ops: Sequence[int] = tuple(range(10))) -> Circuit:
     """Random gates over ``ops`` on random qubits (a generalisation of Alg. 1: the second
     qubit is redrawn until it differs from the first).  Draw order per gate: op, q1,

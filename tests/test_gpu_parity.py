@@ -322,3 +322,14 @@ def test_fused_diagonal_runs_match_oracle(qg, n, dtype):
         qg.set_tuning("diag_run_min", saved)
     for o in out:
         assert np.max(np.abs(o - ref)) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_cx_block_unitary_matches_oracle(qg, dtype):
+    """A random CX-block unitary (the paper's Alg. 1 generator) on 16 qubits."""
+    circ = W.cx_blocks(16, 400, seed=W.SEED_BASE + 9)
+    ref = oracle.simulate(circ)
+    for fusion in (0, 1):
+        st = run(qg, circ, dtype, fusion)
+        assert np.max(np.abs(host(st) - ref)) < TOL[dtype]
+        st.close()

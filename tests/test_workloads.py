@@ -66,3 +66,18 @@ def test_sweep_parts():
     names = [p[0] for p in parts]
     assert names[:30] == [f"u3_t{t}" for t in range(30)]
     assert sum(c.n_gates for _, c in parts) == full.n_gates == 30 + 15 + sum(range(2, 7))
+
+
+def test_cx_blocks_follow_the_generator():
+    """Alg. 1 blocks: RY on the control, RZ on a distinct target, then CX(control -> target);
+    angles in [0, 2 pi); the same seed gives the same circuit."""
+    c = W.cx_blocks(12, 200, seed=3)
+    assert c.n_gates == 600
+    g = c.gate_type.reshape(200, 3, 3)
+    assert np.all(g[:, 0, 0] == W.RY) and np.all(g[:, 1, 0] == W.RZ) and np.all(g[:, 2, 0] == W.CX)
+    qc, qt = g[:, 2, 1], g[:, 2, 2]
+    assert np.all(qc != qt) and np.all(g[:, 0, 2] == qc) and np.all(g[:, 1, 2] == qt)
+    ang = c.gate_param.reshape(200, 3, 3)[:, :2, 0]
+    assert np.all((ang >= 0) & (ang < 2 * np.pi))
+    assert np.array_equal(W.cx_blocks(12, 200, seed=3).gate_param, c.gate_param)
+    assert len(set(map(tuple, np.stack([qc, qt], 1)))) > 100  # pairs drawn with replacement over 132
