@@ -416,7 +416,8 @@ def main():
                      "avg_launch_ms": round(tile_time / len(tile_parts) * 1e3, 4)},
         "sweep": sweep,
         "autotune": {"source": source, "classes": "target <3 | <12 | <20 | >=20 | diagonal",
-                     "tile_reg_swz": table},
+                     "tile_reg_swz": table,
+                     "per_target_tile_reg_swz_xcd": autotune.current_targets(args.dtype)[:n]},
         "cpu_baseline": cpu,
     }
     out.update(extras)

@@ -251,6 +251,9 @@ qg_status qg_set_cost_model(qg_mlp *m);
  *   nt                               non-temporal state loads/stores: 0 off, 1 when every
  *                                    wavefront access covers whole cache lines, 2 always
  *   swz_bits                         tile-order swizzle of the launch
+ *   cls<k>_<tile|reg|swz>_<dt>       shape of pass class k (see qg_autotune)
+ *   tgt<q>_<tile|reg|swz|xcd>_<dt>   shape of single-gate passes on target q (tile 0:
+ *                                    use the class; see qg_autotune)
  *   xcd                              1: each of the 8 XCDs streams a contiguous eighth
  *                                    of a pass's tiles (blocks are dealt to XCDs in
  *                                    turn); 0: block b takes tile b
@@ -274,7 +277,12 @@ qg_status qg_get_tuning(const char *key, int64_t *value);
  * entry for the state's dtype (tuning keys cls<k>_tile_<dt>, cls<k>_reg_<dt>,
  * cls<k>_swz_<dt>; fused passes use the class's swizzle).  The state's
  * amplitudes are overwritten and reset to |0...0> at the end; the call waits
- * for the state's stream.  table: host int32[5][3] (tile, reg, swz) or NULL. */
+ * for the state's stream.  table: host int32[5][3] (tile, reg, swz) or NULL.
+ * Then, per target qubit, single-gate U3 passes are timed for 6 (tile bits,
+ * register bits, swizzle, XCD order) candidates and the fastest becomes that
+ * target's entry (tuning keys tgt<q>_tile_<dt>, tgt<q>_reg_<dt>,
+ * tgt<q>_swz_<dt>, tgt<q>_xcd_<dt>; tile 0 means "use the class"), used by
+ * single-gate passes of one-qubit mixing gates. */
 qg_status qg_autotune(qg_state *s, int reps, int32_t *table);
 
 /* Message describing the calling thread's last failed call ("" if none). */

@@ -1336,6 +1336,53 @@ qg_status qg_autotune(qg_state *s, int reps, int32_t *table) {
         tu.cls_reg[d][cls] = keep.reg;
         tu.cls_swz[d][cls] = keep.swz;
     }
+    // Per target qubit: single-gate passes of a one-qubit mixing gate take the
+    // fastest of a few shapes and tile orders on that target (the best order
+    // depends on the target's address bit: measured 5.7 vs 6.1 TB/s).
+    struct TCand {
+        int tile, reg, swz, xcd;
+    };
+    static const TCand t128[] = {{13, 4, 0, 1}, {13, 4, 4, 0}, {12, 4, 0, 1}, {10, 2, 4, 1}, {10, 2, 0, 1}, {11, 3, 0, 1}};
+    static const TCand t64[] = {{13, 5, 0, 1}, {13, 5, 4, 0}, {12, 4, 0, 1}, {10, 2, 4, 1}, {11, 3, 0, 1}, {12, 5, 4, 1}};
+    const TCand *tc = c64 ? t64 : t128;
+    for (int t = 0; t < n && t < 64 && result == QG_OK; ++t) {
+        Gate g{};
+        g.op = QG_U3;
+        g.q0 = -1;
+        g.q1 = t;
+        g.p[0] = 0.7;
+        g.p[1] = 0.3;
+        g.p[2] = 0.1;
+        g.pidx = -1;
+        const std::vector<Gate> gl{g};
+        double best = 1e300;
+        int keep[4] = {0, 0, 0, 0};
+        for (int k = 0; k < 6 && result == QG_OK; ++k) {
+            if (tc[k].tile > n) continue;
+            int *e = tu.tgt[d][t];
+            e[0] = tc[k].tile, e[1] = tc[k].reg, e[2] = tc[k].swz, e[3] = tc[k].xcd;
+            const Program prog = build_plan(gl, plan_config(n, c64, QG_FUSE_NONE));
+            std::vector<float> ms;
+            for (int r = 0; r <= reps && result == QG_OK; ++r) {
+                hipError_t e2 = hipEventRecord(e0, s->cx.stream);
+                if (e2 == hipSuccess) result = run_program(s->cx, c64, prog, s->buf, nullptr, nullptr);
+                if (result != QG_OK) break;
+                e2 = hipEventRecord(e1, s->cx.stream);
+                if (e2 == hipSuccess) e2 = hipEventSynchronize(e1);
+                float v = 0.f;
+                if (e2 == hipSuccess) e2 = hipEventElapsedTime(&v, e0, e1);
+                if (e2 != hipSuccess) result = hip_fail(e2, "autotune timing");
+                if (r > 0) ms.push_back(v);
+            }
+            if (result != QG_OK) break;
+            std::sort(ms.begin(), ms.end());
+            if (ms[ms.size() / 2] < best) {
+                best = ms[ms.size() / 2];
+                keep[0] = tc[k].tile, keep[1] = tc[k].reg, keep[2] = tc[k].swz, keep[3] = tc[k].xcd;
+            }
+        }
+        for (int f = 0; f < 4; ++f) tu.tgt[d][t][f] = keep[f];
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (result != QG_OK) return result;

@@ -283,8 +283,28 @@ int pass_class(uint64_t required, bool c64) {
 }
 
 namespace {
+// "tgt<q>_<tile|reg|swz|xcd>_<c128|c64>"
+int *target_knob(const char *key, int *lo, int *hi) {
+    int q = -1;
+    char what[8] = {0}, dt[8] = {0};
+    if (std::sscanf(key, "tgt%d_%7[a-z]_%7[a-z0-9]", &q, what, dt) != 3) return nullptr;
+    if (q < 0 || q >= 64) return nullptr;
+    const int d = std::strcmp(dt, "c128") == 0 ? 0 : std::strcmp(dt, "c64") == 0 ? 1 : -1;
+    if (d < 0) return nullptr;
+    static const char *names[4] = {"tile", "reg", "swz", "xcd"};
+    static const int los[4] = {0, 1, 0, 0}, his[4] = {13, 5, 16, 1};
+    for (int f = 0; f < 4; ++f)
+        if (std::strcmp(what, names[f]) == 0) {
+            *lo = los[f];
+            *hi = f == 1 && d == 0 ? 4 : his[f];
+            return &tuning().tgt[d][q][f];
+        }
+    return nullptr;
+}
+
 // "cls<k>_<tile|reg|swz>_<c128|c64>"
 int *class_knob(const char *key, int *lo, int *hi) {
+    if (int *f = target_knob(key, lo, hi)) return f;
     int k = -1;
     char what[8] = {0}, dt[8] = {0};
     if (std::sscanf(key, "cls%d_%7[a-z]_%7[a-z0-9]", &k, what, dt) != 3) return nullptr;
@@ -647,12 +667,21 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
         const int dcls = cfg.c64 ? 1 : 0;
         const int cls = pass_class(req, cfg.c64);
         int tile_bits = cfg.tile_bits, reg_bits = cfg.reg_bits, swz_bits = cfg.swz_bits;
+        int xcd = tu.xcd;
         if (cfg.use_classes && !cfg.reverse) {
             if (r.g_end - r.g_begin == 1) {
                 tile_bits = tu.cls_tile[dcls][cls];
                 reg_bits = tu.cls_reg[dcls][cls];
             }
             swz_bits = tu.cls_swz[dcls][cls];
+            const Gate &g0 = gates[r.g_begin];
+            if (r.g_end - r.g_begin == 1 && is_one_qubit(g0.op) && g0.op != QG_RZ && tu.tgt[dcls][g0.q1][0] > 0) {
+                const int *e = tu.tgt[dcls][g0.q1];
+                tile_bits = e[0];
+                reg_bits = e[1];
+                swz_bits = e[2];
+                xcd = e[3];
+            }
         }
         // ---- tile: required qubits, then the lowest remaining ones
         const int b = std::min(n, std::max(tile_bits, popcount64(req)));
@@ -701,7 +730,7 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
         }
         pd.n_tiles = 1ull << free_bits;
         pd.swz_bits = std::min(swz_bits, free_bits / 2);
-        if (tu.xcd && free_bits >= 3) pd.flags |= PASS_XCD;
+        if (xcd && free_bits >= 3) pd.flags |= PASS_XCD;
         pd.phase_begin = (int)prog.phases.size();
 
         // ---- phases: register positions must hold every mixing op's target

@@ -65,6 +65,9 @@ struct Tuning {
     int cls_tile[2][kPassClasses] = {{12, 12, 12, 10, 12}, {13, 13, 13, 11, 13}};
     int cls_reg[2][kPassClasses] = {{4, 4, 4, 2, 4}, {5, 5, 5, 3, 5}};
     int cls_swz[2][kPassClasses] = {{4, 4, 4, 0, 4}, {4, 4, 4, 0, 4}};
+    // Per target qubit, for single-gate passes of a one-qubit mixing gate:
+    // {tile bits, register bits, swizzle, xcd order}; tile 0 = use the class.
+    int tgt[2][64][4] = {};
 };
 Tuning &tuning();
 // Returns 0 on success, -1 for an unknown key or out-of-range value.

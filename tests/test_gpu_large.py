@@ -134,7 +134,7 @@ def test_bench_sweep_at_full_size_sampled_amplitudes(qg, n, dtype, tmp_path, mon
     share six qubits, everything else is single-qubit)."""
     from paper_2504_03967_amd import autotune
     monkeypatch.setenv("QG_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
-    before = autotune.current(dtype)
+    before = autotune.snapshot(dtype)
     try:
         autotune.tuned(n, dtype)
         prep, full, parts = W.sweep(n)
@@ -151,4 +151,4 @@ def test_bench_sweep_at_full_size_sampled_amplitudes(qg, n, dtype, tmp_path, mon
         assert abs(terms.cpu().numpy()[0] - 1) < TOL[dtype]
         st.close()
     finally:
-        autotune.apply(before, dtype)
+        autotune.restore(before, dtype)
