@@ -339,10 +339,9 @@ def main():
     for name, _ in parts:
         if not name.startswith("u3"):
             sweep[name + "_GBps"] = round(algo_frac(name) * pass_bytes / float(np.mean(per[name])) / 1e9, 1)
-    # Dominant kernel: the tile pass (every part except the standalone SWAPs of two qubits
-    # above the line bits, which run the permutation kernel).
-    tile_parts = [nm for nm, _ in parts
-                  if not (nm.startswith("swap") and algo_frac(nm) == 0.5)]
+    # Dominant kernel: the tile pass (every part except the standalone SWAPs, which run the
+    # permutation kernels).
+    tile_parts = [nm for nm, _ in parts if not nm.startswith("swap")]
     tile_bytes = sum(algo_frac(nm) * pass_bytes for nm in tile_parts)
     tile_time = sum(float(np.mean(per[nm])) for nm in tile_parts)
     achieved = tile_bytes / tile_time / 1e9

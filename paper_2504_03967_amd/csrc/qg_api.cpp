@@ -171,7 +171,7 @@ size_t amp_bytes(qg_dtype dt) { return dt == QG_C64 ? 8 : 16; }
 int max_qubits(qg_dtype dt) { return dt == QG_C64 ? 34 : 33; }
 
 bool fits_inline(const Program &prog, const PassDesc &pd) {
-    if (pd.flags & PASS_SWAP2) return true;  // no program needed
+    if (pd.flags & (PASS_SWAP2 | PASS_SWAPL)) return true;  // no program needed
     if ((pd.flags & PASS_DENSE) || pd.n_phase > kInlinePhases) return false;
     const PhaseDesc &first = prog.phases[pd.phase_begin];
     const PhaseDesc &last = prog.phases[pd.phase_begin + pd.n_phase - 1];
@@ -228,9 +228,12 @@ qg_status run_program(Ctx &cx, bool c64, const Program &prog, void *psi, void *l
     InlineProg inl;
     for (size_t p = 0; p < prog.passes.size(); ++p) {
         const PassDesc &pd = prog.passes[p];
-        if (pd.flags & PASS_SWAP2) {
+        if (pd.flags & (PASS_SWAP2 | PASS_SWAPL)) {
             const int n = __builtin_ctzll(pd.n_tiles) + 2;
-            HIP_TRY(launch_swap2(c64, psi, n, pd.run_start[0], pd.run_start[1], (pd.flags & PASS_XCD) != 0, cx.stream), "swap kernel launch");
+            const bool xcd = (pd.flags & PASS_XCD) != 0;
+            HIP_TRY((pd.flags & PASS_SWAP2) ? launch_swap2(c64, psi, n, pd.run_start[0], pd.run_start[1], xcd, cx.stream)
+                                            : launch_swap_lane(c64, psi, n, pd.run_start[0], pd.run_start[1], xcd, cx.stream),
+                    "swap kernel launch");
             continue;
         }
         if (pd.flags & PASS_DENSE) {

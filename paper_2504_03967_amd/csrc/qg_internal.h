@@ -103,6 +103,8 @@ enum PassFlags : int32_t {
     PASS_SWAP2 = 4,  // the pass is a standalone SWAP of qubits run_start[0] and run_start[1]
     PASS_XCD = 8,    // tile order: block b takes tile (b mod 8) * n_tiles / 8 + b / 8
     PASS_PIPE = 16,  // persistent blocks that load their next tile while computing the current one
+    PASS_SWAPL = 64, // standalone SWAP of qubits run_start[0], run_start[1] with the lower one
+                     // inside a cache line: coalesced loads and a cross-lane exchange
 };
 
 // A dense k-qubit block (k in 4..6): tiles are the block qubits blk_q plus the l

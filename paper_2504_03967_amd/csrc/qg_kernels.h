@@ -56,6 +56,8 @@ hipError_t launch_dense(bool c64, const DenseDesc &D, const void *ut_re, const v
 // SWAP of qubits a and b as a permutation of the amplitudes whose bits differ.
 // xcd: deal contiguous eighths of the pair range to the 8 XCDs (blocks go to XCDs in turn).
 hipError_t launch_swap2(bool c64, void *psi, int n, int a, int b, bool xcd, hipStream_t st);
+// SWAP whose lower qubit is a lane bit (< 6); n >= 12.
+hipError_t launch_swap_lane(bool c64, void *psi, int n, int a, int b, bool xcd, hipStream_t st);
 
 // Batched persistent launch (all pointers are device pointers).
 struct BatchLaunch {

@@ -1,7 +1,13 @@
-// qg_perm.hip -- SWAP of two qubits as a pure permutation: only the amplitudes
-// whose two bits differ move (half the state), each exchanged with its partner.
-// Used for a standalone SWAP whose lower qubit is at or above the cache-line
-// offset bits, so every wavefront access covers whole 128-byte lines.
+// qg_perm.hip -- SWAP of two qubits as a pure permutation.
+//
+// k_swap2: only the amplitudes whose two bits differ move (half the state),
+// each exchanged with its partner.  Used for a standalone SWAP whose lower
+// qubit is at or above the cache-line offset bits, so every wavefront access
+// covers whole 128-byte lines.
+//
+// k_swap_lane: the lower qubit lies inside a cache line, so every line holds
+// moving amplitudes and the whole state is streamed.  Each wavefront loads 64
+// consecutive amplitudes (coalesced) and exchanges partners across lanes.
 #include "qg_kernels.h"
 
 namespace qg {
@@ -38,7 +44,84 @@ __global__ void __launch_bounds__(256) k_swap2(C *__restrict__ psi, int lo, int 
     }
 }
 
+// Lane bits: the lower SWAP qubit lo < 6 is a lane bit of every wavefront access.
+// hi < 6 too: one load per element, partner = lane with bits lo and hi exchanged.
+// hi >= 6: pair p holds amplitude i0 (bit hi = 0) and i1 = i0 | 2^hi, both on the
+// same lane; an i0 with bit lo set swaps with the i1 of the lane across bit lo.
+template <typename C, int U>
+__global__ void __launch_bounds__(256) k_swap_lane(C *__restrict__ psi, int lo, int hi, uint64_t n_items,
+                                                   int xcd_shift) {
+    uint64_t blk = blockIdx.x;
+    if (xcd_shift > 0) blk = ((blk & 7) << xcd_shift) | (blk >> 3);  // gridDim.x = 8 << xcd_shift
+    const uint64_t base = blk * blockDim.x * U + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int mlo = 1 << lo;
+    const bool blo = (lane >> lo) & 1;
+    if (hi < 6) {
+        const bool moves = blo != (((lane >> hi) & 1) != 0);
+        const int mask = mlo | (1 << hi);
+        C v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = psi[base + (uint64_t)u * blockDim.x];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            C w;
+            w.x = __shfl_xor(v[u].x, mask, 64);
+            w.y = __shfl_xor(v[u].y, mask, 64);
+            if (moves) v[u] = w;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) psi[base + (uint64_t)u * blockDim.x] = v[u];
+    } else {
+        const uint64_t bh = 1ull << hi;
+        C v0[U], v1[U];
+        uint64_t i0[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t p = base + (uint64_t)u * blockDim.x;
+            i0[u] = ((p >> hi) << (hi + 1)) | (p & (bh - 1));
+            v0[u] = psi[i0[u]];
+            v1[u] = psi[i0[u] | bh];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            C a, b;
+            a.x = __shfl_xor(v1[u].x, mlo, 64);
+            a.y = __shfl_xor(v1[u].y, mlo, 64);
+            b.x = __shfl_xor(v0[u].x, mlo, 64);
+            b.y = __shfl_xor(v0[u].y, mlo, 64);
+            if (blo) v0[u] = a;
+            else v1[u] = b;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            psi[i0[u]] = v0[u];
+            psi[i0[u] | bh] = v1[u];
+        }
+    }
+    (void)n_items;
+}
+
 }  // namespace
+
+hipError_t launch_swap_lane(bool c64, void *psi, int n, int a, int b, bool xcd, hipStream_t st) {
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    if (a == b || lo < 0 || hi >= n || lo >= 6 || n < 12) return hipErrorInvalidValue;
+    constexpr int U = 4;
+    // items: amplitudes (hi < 6) or pairs (hi >= 6); 256 * U per block, a power of two
+    const uint64_t items = hi < 6 ? (1ull << n) : (1ull << (n - 1));
+    const uint64_t grid = items / (256ull * U);
+    if (grid == 0 || grid > 0x7fffffffull) return hipErrorInvalidValue;
+    int xcd_shift = 0;
+    if (xcd && grid >= 16) xcd_shift = 63 - __builtin_clzll(grid) - 3;
+    if (c64)
+        hipLaunchKernelGGL((k_swap_lane<float2, U>), dim3((uint32_t)grid), dim3(256), 0, st,
+                           static_cast<float2 *>(psi), lo, hi, items, xcd_shift);
+    else
+        hipLaunchKernelGGL((k_swap_lane<double2, U>), dim3((uint32_t)grid), dim3(256), 0, st,
+                           static_cast<double2 *>(psi), lo, hi, items, xcd_shift);
+    return hipGetLastError();
+}
 
 hipError_t launch_swap2(bool c64, void *psi, int n, int a, int b, bool xcd, hipStream_t st) {
     if (a == b || a < 0 || b < 0 || a >= n || b >= n || n < 2) return hipErrorInvalidValue;

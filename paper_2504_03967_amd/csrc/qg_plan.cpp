@@ -147,6 +147,7 @@ const Knob kKnobs[] = {
     {"xcd", [](Tuning &t) { return &t.xcd; }, 0, 1},
     {"pipe", [](Tuning &t) { return &t.pipe; }, 0, 2},
     {"diag_run_min", [](Tuning &t) { return &t.diag_run_min; }, 0, 1 << 20},
+    {"lane_swap", [](Tuning &t) { return &t.lane_swap; }, 0, 1},
     {"pipe_min_ops", [](Tuning &t) { return &t.pipe_min_ops; }, 1, 1 << 20},
     {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 1, 1 << 30},
 };
@@ -292,7 +293,7 @@ int *target_knob(const char *key, int *lo, int *hi) {
     const int d = std::strcmp(dt, "c128") == 0 ? 0 : std::strcmp(dt, "c64") == 0 ? 1 : -1;
     if (d < 0) return nullptr;
     static const char *names[4] = {"tile", "reg", "swz", "xcd"};
-    static const int los[4] = {0, 1, 0, 0}, his[4] = {13, 5, 16, 1};
+    static const int los[4] = {0, 0, 0, 0}, his[4] = {13, 5, 16, 1};  // all 0: unset
     for (int f = 0; f < 4; ++f)
         if (std::strcmp(what, names[f]) == 0) {
             *lo = los[f];
@@ -675,7 +676,8 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
             }
             swz_bits = tu.cls_swz[dcls][cls];
             const Gate &g0 = gates[r.g_begin];
-            if (r.g_end - r.g_begin == 1 && is_one_qubit(g0.op) && g0.op != QG_RZ && tu.tgt[dcls][g0.q1][0] > 0) {
+            if (r.g_end - r.g_begin == 1 && is_one_qubit(g0.op) && g0.op != QG_RZ && tu.tgt[dcls][g0.q1][0] > 0 &&
+                tu.tgt[dcls][g0.q1][1] > 0) {
                 const int *e = tu.tgt[dcls][g0.q1];
                 tile_bits = e[0];
                 reg_bits = e[1];
@@ -980,11 +982,17 @@ Program build_plan(const std::vector<Gate> &g0, const PlanConfig &cfg, std::vect
     const std::vector<Gate> g = permute(g0, sc.order);
     const std::vector<PassRange> &ranges = sc.ranges;
     const int line_bits = cfg.c64 ? 4 : 3;
+    // Standalone SWAPs run as permutations: half the state when both qubits are
+    // at or above the line bits, otherwise (lower qubit a lane bit) the whole
+    // state with a cross-lane exchange.
+    auto swap_kind = [&](const PassRange &r) -> int {
+        if (cfg.reverse || r.g_end - r.g_begin != 1 || g[r.g_begin].op != QG_SWAP) return 0;
+        const int lo = std::min(g[r.g_begin].q0, g[r.g_begin].q1);
+        if (lo >= line_bits) return PASS_SWAP2;
+        return cfg.n >= 12 && tuning().lane_swap ? PASS_SWAPL : 0;
+    };
     bool special = false;
-    for (const PassRange &r : ranges)
-        if (r.g_end - r.g_begin == 1 && g[r.g_begin].op == QG_SWAP &&
-            std::min(g[r.g_begin].q0, g[r.g_begin].q1) >= line_bits)
-            special = true;
+    for (const PassRange &r : ranges) special |= swap_kind(r) != 0;
     // Adjoint sweeps number their gradient rows across the whole program: one build.
     if (cfg.reverse || (!special && (cfg.dense_min_gates >= (1 << 30) || cfg.n < 8)))
         return build_program(g, ranges, cfg);
@@ -993,10 +1001,9 @@ Program build_plan(const std::vector<Gate> &g0, const PlanConfig &cfg, std::vect
     for (size_t p = 0; p < ranges.size(); ++p) {
         const PassRange &r = ranges[p];
         const Gate &g1 = g[r.g_begin];
-        if (!cfg.reverse && r.g_end - r.g_begin == 1 && g1.op == QG_SWAP && std::min(g1.q0, g1.q1) >= line_bits) {
-            // standalone SWAP: move only the half of the state whose two bits differ
+        if (const int kind = swap_kind(r)) {
             PassDesc pd{};
-            pd.flags = PASS_SWAP2 | (tuning().xcd ? PASS_XCD : 0);
+            pd.flags = kind | (tuning().xcd ? PASS_XCD : 0);
             pd.run_start[0] = g1.q0;
             pd.run_start[1] = g1.q1;
             pd.n_tiles = 1ull << (cfg.n - 2);
@@ -1022,7 +1029,7 @@ void append_program(Program *dst, const Program &src) {
     const int d0 = (int)dst->dense.size();
     const int64_t u0 = (int64_t)dst->dense_ut.size();
     for (PassDesc pd : src.passes) {
-        if (!(pd.flags & PASS_SWAP2)) pd.phase_begin += (pd.flags & PASS_DENSE) ? d0 : ph0;
+        if (!(pd.flags & (PASS_SWAP2 | PASS_SWAPL))) pd.phase_begin += (pd.flags & PASS_DENSE) ? d0 : ph0;
         dst->passes.push_back(pd);
     }
     for (DenseDesc d : src.dense) {

@@ -333,3 +333,32 @@ def test_cx_block_unitary_matches_oracle(qg, dtype):
         st = run(qg, circ, dtype, fusion)
         assert np.max(np.abs(host(st) - ref)) < TOL[dtype]
         st.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [12, 16])
+def test_standalone_swaps_as_permutations(qg, n, dtype):
+    """Standalone SWAPs run as permutation kernels (half the state when both qubits are above
+    the cache-line bits, a cross-lane exchange when the lower one is inside a line): against
+    the oracle, and bit for bit against the same SWAPs run as tile passes."""
+    pairs = [(0, 1), (1, 2), (2, 0), (0, 5), (3, 4), (1, n - 1), (n - 1, 4), (5, 6), (6, n - 2), (2, 7)]
+    b = W.CircuitBuilder(n)
+    prep = prep_layer(n, 300 + n)
+    for (o, q0, q1), p in zip(prep.gate_type, prep.gate_param):
+        b.add(o, q0, q1, p)
+    for x, y in pairs:
+        b.g2(W.SWAP, x, y)
+    circ = b.build()
+    ref = oracle.simulate(circ)
+    saved = qg.get_tuning("lane_swap")
+    out = []
+    try:
+        for lane in (1, 0):
+            qg.set_tuning("lane_swap", lane)
+            st = run(qg, circ, dtype, 0)
+            out.append(host(st))
+            st.close()
+    finally:
+        qg.set_tuning("lane_swap", saved)
+    assert np.max(np.abs(out[0] - ref)) < TOL[dtype]
+    assert np.array_equal(out[0], out[1])
