@@ -66,7 +66,7 @@ typedef enum {
     QG_FUSE_NONE = 0,    /* one device pass per gate */
     QG_FUSE_GREEDY = 1,  /* greedy fixed-width fusion: a pass holds gates whose non-diagonal
                             targets span at most 5 qubits outside the low, always-resident
-                            tile qubits (the paper's gate fusion = 5, App. D.2); gates on
+                            tile qubits (the fusion width 5 of App. D.2); gates on
                             disjoint qubits commute, so each pass takes every pending gate
                             that fits and is not blocked by an earlier gate on its qubits */
     QG_FUSE_LEARNED = 2  /* cost-model planner (qg_mlp_*); falls back to greedy without a model */
@@ -145,7 +145,7 @@ qg_status qg_expval(qg_state *s, const uint64_t *zmask, const double *coeff, int
 
 /* Value and gradient of f = sum_m coeff[m] <Z_{zmask[m]}> for the circuit applied
  * to |0...0>, by one adjoint reverse sweep (Jones & Gacon 2020; the paper's
- * "adjoint GPU modes", Sec. 2): for each gate with param_idx >= 0, RX/RY/RZ add
+ * adjoint GPU modes, Sec. 2): for each gate with param_idx >= 0, RX/RY/RZ add
  * Im<lambda|P|psi> and CP adds -2 Im<lambda|P11|psi> to grad[param_idx].
  * The library allocates the two working states and releases them before
  * returning.  out_value: device scalar; out_grad: device [n_params].
