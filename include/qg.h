@@ -262,6 +262,11 @@ qg_status qg_set_cost_model(qg_mlp *m);
  *                                    0 never, 1 passes with several register layouts
  *                                    or at least pipe_min_ops ops, 2 always
  *   pipe_min_ops                     see pipe
+ *   diag_run_min                     runs of at least this many consecutive diagonal
+ *                                    gates in a register layout become one factor per
+ *                                    amplitude (0: never)
+ *   lane_swap                        1: a standalone SWAP whose lower qubit lies inside
+ *                                    a cache line runs as a cross-lane exchange kernel
  * Errors: QG_EINVAL for an unknown key or a value out of range.  Not
  * thread-safe against concurrent planning. */
 qg_status qg_set_tuning(const char *key, int64_t value);
