@@ -339,9 +339,11 @@ def main():
     for name, _ in parts:
         if not name.startswith("u3"):
             sweep[name + "_GBps"] = round(algo_frac(name) * pass_bytes / float(np.mean(per[name])) / 1e9, 1)
-    # Dominant kernel: the tile pass (every part except the standalone SWAPs, which run the
-    # permutation kernels).
-    tile_parts = [nm for nm, _ in parts if not nm.startswith("swap")]
+    # Dominant kernel: the tile pass.  The planner sends standalone SWAPs to the permutation
+    # kernels and single gates with their target inside a cache line to the lane kernel; those
+    # parts stay out of the tile-pass figure.
+    kernels_of = {nm: qg.plan_kernels(c, args.dtype, modes(nm)) for nm, c in parts}
+    tile_parts = [nm for nm, _ in parts if set(kernels_of[nm]) == {"tile"}]
     tile_bytes = sum(algo_frac(nm) * pass_bytes for nm in tile_parts)
     tile_time = sum(float(np.mean(per[nm])) for nm in tile_parts)
     achieved = tile_bytes / tile_time / 1e9
@@ -411,6 +413,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_tile_inl (tile pass)", "launches_per_step": len(tile_parts),
+                     "other_parts": {k: sorted(set(v)) for k, v in kernels_of.items() if set(v) != {"tile"}},
                      "algorithmic_bytes_per_launch": round(bytes_per_launch),
                      "avg_launch_ms": round(tile_time / len(tile_parts) * 1e3, 4)},
         "sweep": sweep,

@@ -193,6 +193,21 @@ qg_status qg_batch_free(qg_batch *b);
 qg_status qg_plan_passes(const qg_circuit *c, qg_dtype dtype, int fusion_mode,
                          int32_t *pass_of_gate, int32_t *n_passes);
 
+/* Kernel family that runs each pass of qg_apply_circuit's plan (host only, no
+ * device needed): kernel_of_pass[min(capacity, passes)] (host, may be NULL)
+ * gets one qg_kernel code per pass, in execution order, and *n_passes the pass
+ * count.  The choice follows the current tuning keys (lane_swap, lane_gate,
+ * dense_min_gates). */
+typedef enum {
+    QG_KERNEL_TILE = 0,       /* tile pass: gates applied in registers, layouts exchanged through LDS */
+    QG_KERNEL_DENSE = 1,      /* dense k-qubit block (fused unitary) */
+    QG_KERNEL_SWAP_HALF = 2,  /* SWAP of two qubits above the cache-line bits: half the state moves */
+    QG_KERNEL_SWAP_LANE = 3,  /* SWAP with its lower qubit inside a cache line: cross-lane exchange */
+    QG_KERNEL_LANE_GATE = 4   /* one-qubit gate or CX with its target inside a cache line */
+} qg_kernel;
+qg_status qg_plan_kernels(const qg_circuit *c, qg_dtype dtype, int fusion_mode,
+                          int32_t *kernel_of_pass, int32_t capacity, int32_t *n_passes);
+
 /* ---- Learned fusion: the cost model (not in the paper; its backend fixes the
  * fusion width at 5, App. D.2).  An MLP with three ReLU hidden layers of width
  * 64 and a linear scalar output, FP32, run by the library's own forward,
@@ -267,6 +282,8 @@ qg_status qg_set_cost_model(qg_mlp *m);
  *                                    amplitude (0: never)
  *   lane_swap                        1: a standalone SWAP whose lower qubit lies inside
  *                                    a cache line runs as a cross-lane exchange kernel
+ *   lane_gate                        1: a single one-qubit gate or CX whose target lies
+ *                                    inside a cache line runs as a cross-lane exchange
  * Errors: QG_EINVAL for an unknown key or a value out of range.  Not
  * thread-safe against concurrent planning. */
 qg_status qg_set_tuning(const char *key, int64_t value);

@@ -171,7 +171,7 @@ size_t amp_bytes(qg_dtype dt) { return dt == QG_C64 ? 8 : 16; }
 int max_qubits(qg_dtype dt) { return dt == QG_C64 ? 34 : 33; }
 
 bool fits_inline(const Program &prog, const PassDesc &pd) {
-    if (pd.flags & (PASS_SWAP2 | PASS_SWAPL)) return true;  // no program needed
+    if (pd.flags & (PASS_SWAP2 | PASS_SWAPL | PASS_LANE1)) return true;  // no program needed
     if ((pd.flags & PASS_DENSE) || pd.n_phase > kInlinePhases) return false;
     const PhaseDesc &first = prog.phases[pd.phase_begin];
     const PhaseDesc &last = prog.phases[pd.phase_begin + pd.n_phase - 1];
@@ -228,6 +228,15 @@ qg_status run_program(Ctx &cx, bool c64, const Program &prog, void *psi, void *l
     InlineProg inl;
     for (size_t p = 0; p < prog.passes.size(); ++p) {
         const PassDesc &pd = prog.passes[p];
+        if (pd.flags & PASS_LANE1) {
+            const int n = __builtin_ctzll(pd.n_tiles) + 2;
+            LaneGateArgs la{};
+            std::memcpy(la.m, prog.ops[pd.phase_begin].m, sizeof la.m);
+            la.t = pd.run_start[0];
+            la.c = pd.run_start[1];
+            HIP_TRY(launch_lane_gate(c64, psi, n, la, (pd.flags & PASS_XCD) != 0, cx.stream), "lane gate launch");
+            continue;
+        }
         if (pd.flags & (PASS_SWAP2 | PASS_SWAPL)) {
             const int n = __builtin_ctzll(pd.n_tiles) + 2;
             const bool xcd = (pd.flags & PASS_XCD) != 0;
@@ -755,6 +764,40 @@ qg_status qg_plan_passes(const qg_circuit *c, qg_dtype dtype, int fusion_mode, i
         for (int i = r[p].g_begin; i < r[p].g_end; ++i)
             if (pass_of_gate) pass_of_gate[order.empty() ? i : order[i]] = (int32_t)p;
     if (n_passes) *n_passes = (int32_t)r.size();
+    return QG_OK;
+}
+
+qg_status qg_plan_kernels(const qg_circuit *c, qg_dtype dtype, int fusion_mode, int32_t *kernel_of_pass,
+                          int32_t capacity, int32_t *n_passes) {
+    std::string err;
+    if (validate_circuit(c, -1, &err) != QG_OK) return fail(QG_EINVAL, "%s", err.c_str());
+    if (fusion_mode < QG_FUSE_NONE || fusion_mode > QG_FUSE_LEARNED)
+        return fail(QG_EINVAL, "unknown fusion mode %d", fusion_mode);
+    if (dtype != QG_C64 && dtype != QG_C128) return fail(QG_EINVAL, "unknown dtype %d", (int)dtype);
+    if (capacity < 0) return fail(QG_EINVAL, "capacity < 0");
+    const bool c64 = dtype == QG_C64;
+    Program prog;
+    if (c->n_gates > 0) {
+        std::vector<Gate> g = load_gates(c);
+        if (fusion_mode == QG_FUSE_LEARNED) {
+            PlanEntry e;
+            qg_status st = learned_plan(g, c->n_qubits, c64, &e);
+            if (st != QG_OK) return st;
+            prog = build_learned(g, e, c->n_qubits, c64);
+        } else {
+            prog = build_plan(g, plan_config(c->n_qubits, c64, fusion_mode));
+        }
+    }
+    const int32_t np = (int32_t)prog.passes.size();
+    for (int32_t p = 0; p < np && p < capacity && kernel_of_pass; ++p) {
+        const int32_t f = prog.passes[p].flags;
+        kernel_of_pass[p] = (f & PASS_LANE1)   ? QG_KERNEL_LANE_GATE
+                            : (f & PASS_SWAPL) ? QG_KERNEL_SWAP_LANE
+                            : (f & PASS_SWAP2) ? QG_KERNEL_SWAP_HALF
+                            : (f & PASS_DENSE) ? QG_KERNEL_DENSE
+                                               : QG_KERNEL_TILE;
+    }
+    if (n_passes) *n_passes = np;
     return QG_OK;
 }
 

@@ -105,6 +105,9 @@ enum PassFlags : int32_t {
     PASS_PIPE = 16,  // persistent blocks that load their next tile while computing the current one
     PASS_SWAPL = 64, // standalone SWAP of qubits run_start[0], run_start[1] with the lower one
                      // inside a cache line: coalesced loads and a cross-lane exchange
+    PASS_LANE1 = 128,// single one-qubit gate (or CX) whose target run_start[0] lies inside a
+                     // cache line: cross-lane exchange; run_start[1] = CX control or -1;
+                     // phase_begin indexes the program's op holding the 2x2 matrix
 };
 
 // A dense k-qubit block (k in 4..6): tiles are the block qubits blk_q plus the l

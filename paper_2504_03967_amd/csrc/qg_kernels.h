@@ -58,6 +58,13 @@ hipError_t launch_dense(bool c64, const DenseDesc &D, const void *ut_re, const v
 hipError_t launch_swap2(bool c64, void *psi, int n, int a, int b, bool xcd, hipStream_t st);
 // SWAP whose lower qubit is a lane bit (< 6); n >= 12.
 hipError_t launch_swap_lane(bool c64, void *psi, int n, int a, int b, bool xcd, hipStream_t st);
+// One-qubit gate m = {m00, m01, m10, m11} (re, im pairs) on target t < 6, or a
+// CX with control c >= 0 (m unused); n >= 12.
+struct LaneGateArgs {
+    double m[8];
+    int t, c;
+};
+hipError_t launch_lane_gate(bool c64, void *psi, int n, const LaneGateArgs &g, bool xcd, hipStream_t st);
 
 // Batched persistent launch (all pointers are device pointers).
 struct BatchLaunch {

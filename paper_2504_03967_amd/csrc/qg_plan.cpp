@@ -148,6 +148,7 @@ const Knob kKnobs[] = {
     {"pipe", [](Tuning &t) { return &t.pipe; }, 0, 2},
     {"diag_run_min", [](Tuning &t) { return &t.diag_run_min; }, 0, 1 << 20},
     {"lane_swap", [](Tuning &t) { return &t.lane_swap; }, 0, 1},
+    {"lane_gate", [](Tuning &t) { return &t.lane_gate; }, 0, 1},
     {"pipe_min_ops", [](Tuning &t) { return &t.pipe_min_ops; }, 1, 1 << 20},
     {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 1, 1 << 30},
 };
@@ -991,8 +992,15 @@ Program build_plan(const std::vector<Gate> &g0, const PlanConfig &cfg, std::vect
         if (lo >= line_bits) return PASS_SWAP2;
         return cfg.n >= 12 && tuning().lane_swap ? PASS_SWAPL : 0;
     };
+    // A single one-qubit mixing gate or CX whose target lies inside a cache line
+    // runs as a cross-lane exchange with whole-line accesses.
+    auto lane_gate = [&](const PassRange &r) {
+        if (cfg.reverse || r.g_end - r.g_begin != 1 || cfg.n < 12 || !tuning().lane_gate) return false;
+        const Gate &x = g[r.g_begin];
+        return ((is_one_qubit(x.op) && x.op != QG_RZ) || x.op == QG_CX) && x.q1 < line_bits;
+    };
     bool special = false;
-    for (const PassRange &r : ranges) special |= swap_kind(r) != 0;
+    for (const PassRange &r : ranges) special |= swap_kind(r) != 0 || lane_gate(r);
     // Adjoint sweeps number their gradient rows across the whole program: one build.
     if (cfg.reverse || (!special && (cfg.dense_min_gates >= (1 << 30) || cfg.n < 8)))
         return build_program(g, ranges, cfg);
@@ -1001,6 +1009,24 @@ Program build_plan(const std::vector<Gate> &g0, const PlanConfig &cfg, std::vect
     for (size_t p = 0; p < ranges.size(); ++p) {
         const PassRange &r = ranges[p];
         const Gate &g1 = g[r.g_begin];
+        if (lane_gate(r)) {
+            std::vector<Item> its;
+            gate_items(g1, false, -1, &its);
+            DevOp op{};
+            op.kind = its[0].kind;
+            op.g = -1;
+            std::memcpy(op.m, its[0].m, sizeof op.m);
+            PassDesc pd{};
+            pd.flags = PASS_LANE1 | (tuning().xcd ? PASS_XCD : 0);
+            pd.run_start[0] = g1.q1;
+            pd.run_start[1] = g1.op == QG_CX ? g1.q0 : -1;
+            pd.n_tiles = 1ull << (cfg.n - 2);
+            pd.phase_begin = (int)prog.ops.size();
+            prog.ops.push_back(op);
+            prog.passes.push_back(pd);
+            prog.pass_of_gate[r.g_begin] = (int)p;
+            continue;
+        }
         if (const int kind = swap_kind(r)) {
             PassDesc pd{};
             pd.flags = kind | (tuning().xcd ? PASS_XCD : 0);
@@ -1029,7 +1055,8 @@ void append_program(Program *dst, const Program &src) {
     const int d0 = (int)dst->dense.size();
     const int64_t u0 = (int64_t)dst->dense_ut.size();
     for (PassDesc pd : src.passes) {
-        if (!(pd.flags & (PASS_SWAP2 | PASS_SWAPL))) pd.phase_begin += (pd.flags & PASS_DENSE) ? d0 : ph0;
+        if (pd.flags & PASS_LANE1) pd.phase_begin += op0;  // index of its matrix op
+        else if (!(pd.flags & (PASS_SWAP2 | PASS_SWAPL))) pd.phase_begin += (pd.flags & PASS_DENSE) ? d0 : ph0;
         dst->passes.push_back(pd);
     }
     for (DenseDesc d : src.dense) {

@@ -24,7 +24,7 @@ OBS_ZZ_CHAIN, OBS_CSR = 0, 1
 EXPORTS = (
     "qg_state_alloc", "qg_state_free", "qg_state_reset", "qg_state_set_stream", "qg_state_info",
     "qg_apply_circuit", "qg_probs", "qg_sample", "qg_expval", "qg_adjoint_grad", "qg_batch_expval",
-    "qg_plan_passes", "qg_last_error", "qg_version", "qg_set_tuning", "qg_get_tuning",
+    "qg_plan_passes", "qg_plan_kernels", "qg_last_error", "qg_version", "qg_set_tuning", "qg_get_tuning",
     "qg_batch_create", "qg_batch_set_params", "qg_batch_launch", "qg_batch_free",
     "qg_mlp_create", "qg_mlp_n_params", "qg_mlp_set_params", "qg_mlp_get_params", "qg_mlp_forward",
     "qg_mlp_grad", "qg_mlp_adam_step", "qg_mlp_train", "qg_mlp_free", "qg_pass_features", "qg_set_cost_model",
@@ -66,6 +66,7 @@ def _load() -> ctypes.CDLL:
         "qg_adjoint_grad": [P, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, P, P, P],
         "qg_batch_expval": [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P],
         "qg_plan_passes": [P, ctypes.c_int, ctypes.c_int, P, P],
+        "qg_plan_kernels": [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int32, P],
         "qg_batch_create": [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P],
         "qg_batch_set_params": [P, P],
         "qg_batch_launch": [P],
@@ -392,6 +393,20 @@ def plan_passes(circ, dtype="c128", fusion: int = FUSE_GREEDY):
     npass = ctypes.c_int32()
     _check(lib.qg_plan_passes(ca.ptr, _dtype_code(dtype), int(fusion), pog.ctypes.data, ctypes.byref(npass)))
     return pog[:ca.gt.shape[0]], int(npass.value)
+
+
+KERNEL_NAMES = ("tile", "dense", "swap_half", "swap_lane", "lane_gate")
+
+
+def plan_kernels(circ, dtype="c128", fusion: int = FUSE_GREEDY):
+    """Kernel family of each pass of the library's plan, as names from KERNEL_NAMES (host only)."""
+    ca = CircuitArgs(circ)
+    npass = ctypes.c_int32()
+    _check(lib.qg_plan_kernels(ca.ptr, _dtype_code(dtype), int(fusion), None, 0, ctypes.byref(npass)))
+    k = np.zeros(max(npass.value, 1), dtype=np.int32)
+    _check(lib.qg_plan_kernels(ca.ptr, _dtype_code(dtype), int(fusion), k.ctypes.data, k.size,
+                               ctypes.byref(npass)))
+    return [KERNEL_NAMES[v] for v in k[:npass.value]]
 
 
 class QGExpval(torch.autograd.Function):

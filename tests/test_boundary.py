@@ -104,3 +104,40 @@ def test_qubit_count_limits(qg):
         qg.plan_passes(W.Circuit(35, np.zeros((0, 3), np.int32), np.zeros((0, 3)), np.zeros(0, np.int32)))
     with pytest.raises(qg.QGError):
         qg.plan_passes(W.Circuit(0, np.zeros((0, 3), np.int32), np.zeros((0, 3)), np.zeros(0, np.int32)))
+
+
+@pytest.mark.parametrize("dtype,line_bits", [("c128", 3), ("c64", 4)])
+def test_plan_kernels_pick_the_permutation_and_lane_kernels(qg, dtype, line_bits):
+    """One pass per gate without fusion; the kernel of each follows the gate and where its
+    qubits sit relative to the cache-line bits (2^line_bits amplitudes per 128-byte line)."""
+    n = 20
+    b = W.CircuitBuilder(n)
+    want = []
+    for t in range(n):
+        b.g1(W.U3, t, 0.1, 0.2, 0.3)
+        want.append("lane_gate" if t < line_bits else "tile")
+        b.g1(W.RZ, t, 0.4)
+        want.append("tile")
+    for c, t in ((0, 1), (n - 1, 0), (1, n - 1), (8, 9), (line_bits, line_bits - 1)):
+        b.g2(W.CX, c, t)
+        want.append("lane_gate" if t < line_bits else "tile")
+    for x, y in ((0, 1), (2, n - 1), (line_bits, n - 1), (8, 9)):
+        b.g2(W.SWAP, x, y)
+        want.append("swap_half" if min(x, y) >= line_bits else "swap_lane")
+    circ = b.build()
+    saved = {k: qg.get_tuning(k) for k in ("lane_gate", "lane_swap")}
+    try:
+        for k in saved:
+            qg.set_tuning(k, 1)
+        assert qg.plan_kernels(circ, dtype, qg.FUSE_NONE) == want
+        qg.set_tuning("lane_gate", 0)
+        qg.set_tuning("lane_swap", 0)
+        assert qg.plan_kernels(circ, dtype, qg.FUSE_NONE) == [
+            "swap_half" if w == "swap_half" else "tile" for w in want]
+    finally:
+        for k, v in saved.items():
+            qg.set_tuning(k, v)
+    # below 12 qubits every gate stays on the tile pass; fused plans match the pass count
+    assert set(qg.plan_kernels(W.random_circuit(10, 50, seed=3), dtype, qg.FUSE_NONE)) == {"tile"}
+    circ = W.config3(26, layers=5)
+    assert len(qg.plan_kernels(circ, dtype, qg.FUSE_GREEDY)) == qg.plan_passes(circ, dtype, qg.FUSE_GREEDY)[1]

@@ -362,3 +362,33 @@ def test_standalone_swaps_as_permutations(qg, n, dtype):
         qg.set_tuning("lane_swap", saved)
     assert np.max(np.abs(out[0] - ref)) < TOL[dtype]
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [12, 17])
+def test_lane_gates_match_oracle(qg, n, dtype):
+    """Single one-qubit gates and CX whose target lies inside a cache line run as a cross-lane
+    exchange (whole-line accesses): every op on every such target, CX controls below, inside
+    and above the line, against the oracle and against the same gates as tile passes."""
+    lb = 4 if dtype == "c64" else 3
+    rng = np.random.default_rng(n)
+    b = W.CircuitBuilder(n)
+    prep = prep_layer(n, 500 + n)
+    for (o, q0, q1), p in zip(prep.gate_type, prep.gate_param):
+        b.add(o, q0, q1, p)
+    for t in range(lb):
+        for op in (W.H, W.X, W.RX, W.RY, W.U3):
+            b.add(op, -1, t, rng.uniform(0, 2 * math.pi, 3))
+        for c in sorted({(t + 1) % lb, lb, 5, n - 1} - {t}):
+            b.g2(W.CX, c, t)
+    circ = b.build()
+    ref = oracle.simulate(circ)
+    saved = qg.get_tuning("lane_gate")
+    try:
+        for lane in (1, 0):
+            qg.set_tuning("lane_gate", lane)
+            st = run(qg, circ, dtype, 0)
+            assert np.max(np.abs(host(st) - ref)) < TOL[dtype]
+            st.close()
+    finally:
+        qg.set_tuning("lane_gate", saved)
