@@ -284,6 +284,9 @@ qg_status qg_set_cost_model(qg_mlp *m);
  *                                    a cache line runs as a cross-lane exchange kernel
  *   lane_gate                        1: a single one-qubit gate or CX whose target lies
  *                                    inside a cache line runs as a cross-lane exchange
+ *   half_lds_c128, half_lds_c64      1 / 0: multi-phase passes move the tile between
+ *                                    layouts through LDS as real parts, then imaginary
+ *                                    parts (half the LDS per workgroup)
  * Errors: QG_EINVAL for an unknown key or a value out of range.  Not
  * thread-safe against concurrent planning. */
 qg_status qg_set_tuning(const char *key, int64_t value);

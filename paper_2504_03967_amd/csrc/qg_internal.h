@@ -108,6 +108,8 @@ enum PassFlags : int32_t {
     PASS_LANE1 = 128,// single one-qubit gate (or CX) whose target run_start[0] lies inside a
                      // cache line: cross-lane exchange; run_start[1] = CX control or -1;
                      // phase_begin indexes the program's op holding the 2x2 matrix
+    PASS_HALFX = 256,// layout exchanges move real and imaginary parts in turn through
+                     // half the LDS (2^b scalars instead of 2^b complex values)
 };
 
 // A dense k-qubit block (k in 4..6): tiles are the block qubits blk_q plus the l

@@ -149,6 +149,8 @@ const Knob kKnobs[] = {
     {"diag_run_min", [](Tuning &t) { return &t.diag_run_min; }, 0, 1 << 20},
     {"lane_swap", [](Tuning &t) { return &t.lane_swap; }, 0, 1},
     {"lane_gate", [](Tuning &t) { return &t.lane_gate; }, 0, 1},
+    {"half_lds_c128", [](Tuning &t) { return &t.half_lds[0]; }, 0, 1},
+    {"half_lds_c64", [](Tuning &t) { return &t.half_lds[1]; }, 0, 1},
     {"pipe_min_ops", [](Tuning &t) { return &t.pipe_min_ops; }, 1, 1 << 20},
     {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 1, 1 << 30},
 };
@@ -844,6 +846,7 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
         const int n_ops = prog.phases.back().op_end - prog.phases[pd.phase_begin].op_begin;
         if (!cfg.reverse && (tu.pipe == 2 || (tu.pipe == 1 && (pd.n_phase > 1 || n_ops >= tu.pipe_min_ops))))
             pd.flags |= PASS_PIPE;
+        if (pd.n_phase > 1 && tu.half_lds[cfg.c64 ? 1 : 0]) pd.flags |= PASS_HALFX;
         // Non-temporal state accesses only pay when every wavefront load/store
         // covers whole 128-byte lines: the first and last layouts must keep the
         // line-offset tile positions (3 for complex128, 4 for complex64) on lanes.

@@ -59,6 +59,9 @@ struct Tuning {
     int diag_run_min = 3;  // fuse runs of at least this many diagonal ops (0: never)
     int lane_swap = 1;     // standalone SWAP with a qubit inside a cache line: cross-lane kernel
     int lane_gate = 1;     // single gate with its target inside a cache line: cross-lane kernel
+    // Multi-phase passes exchange real and imaginary parts in turn through half
+    // the LDS: [c128, c64].
+    int half_lds[2] = {1, 0};
     int pipe = 0;          // persistent prefetching blocks: 0 never, 1 heavy passes, 2 always
     int pipe_min_ops = 4;  // a pass is heavy with several phases or at least this many ops
     int dense_min_gates = 1 << 30;

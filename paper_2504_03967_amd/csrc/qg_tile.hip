@@ -13,6 +13,14 @@ namespace {
 
 using namespace dev;
 
+// Occupancy floor for the compiler's register budget: the complex128 kernel
+// with 16 amplitudes per thread runs multi-phase passes with half-LDS
+// exchanges at three workgroups per CU when it fits 168 registers.
+template <typename R, int RB, int NS>
+struct TileWaves {
+    static constexpr int value = (sizeof(R) == 8 && RB == 4 && NS == 1) ? 3 : 1;
+};
+
 template <typename R, int RB, int NS>
 __device__ __forceinline__ void tile_pass(const PassDesc &P, const PhaseDesc *__restrict__ phases,
                                           const DevOp *__restrict__ ops, const DiagTables &dt,
@@ -92,7 +100,7 @@ __global__ void __launch_bounds__(256) k_tile_inl_pipe(const InlineProg prog, ty
 }
 
 template <typename R, int RB, int NS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TileWaves<R, RB, NS>::value)))
 k_tile(const unsigned char *__restrict__ dev, const ProgOffsets offs, int pass_idx,
        typename V2<R>::T *__restrict__ psi, typename V2<R>::T *__restrict__ lam, double *__restrict__ gpart,
        int64_t gstride) {
@@ -138,7 +146,7 @@ template <typename R, int RB, int NS>
 hipError_t launch_one(const PassDesc &hp, const InlineProg *inl, const void *dev, const ProgOffsets &offs,
                       int pass_idx, void *psi, void *lam, double *gpart, int64_t gstride, hipStream_t st) {
     using C = typename V2<R>::T;
-    const size_t lds = hp.n_phase > 1 ? (size_t(1) << hp.b) * sizeof(C) : 0;
+    const size_t lds = hp.n_phase > 1 ? (size_t(1) << hp.b) * ((hp.flags & PASS_HALFX) ? sizeof(R) : sizeof(C)) : 0;
     const bool pipe = NS == 1 && (hp.flags & PASS_PIPE);
     if (lds > 65536) {
         static bool done = false;

@@ -29,6 +29,14 @@ __device__ __forceinline__ uint32_t swz(uint32_t p) {
     return p ^ ((p >> S) & ((1u << S) - 1));
 }
 
+// The same XOR map for a tile held as separate real or imaginary parts (slots
+// of sizeof(R) bytes: 2^S of them span the 256 bytes of all LDS banks).
+template <typename R>
+__device__ __forceinline__ uint32_t swz_half(uint32_t p) {
+    constexpr uint32_t S = sizeof(R) == 8 ? 5 : 6;
+    return p ^ ((p >> S) & ((1u << S) - 1));
+}
+
 template <typename C, typename R>
 __device__ __forceinline__ void mat2(const R (&m)[8], C v0, C v1, C &o0, C &o1) {
     o0.x = m[0] * v0.x - m[1] * v0.y + m[2] * v1.x - m[3] * v1.y;
@@ -578,9 +586,49 @@ __device__ __forceinline__ void tile_phases(const PassDesc &P, const PhaseDesc *
             // (readfirstlane keeps the uniform term from being folded back into
             // the per-thread expression.)  Offsets are in bytes.
             const PhaseDesc &prev = phases[p - 1];
+            unsigned char *lb = reinterpret_cast<unsigned char *>(lds);
+            if (P.flags & PASS_HALFX) {
+                // Half the LDS: the real parts go through first, then the
+                // imaginary parts (twice the barriers, half the bytes per
+                // workgroup, so more workgroups fit on a CU).
+                constexpr uint32_t SZ = sizeof(R);
+                const uint32_t sq = swz_half<R>(thread_poff(prev, tb, tid)) * SZ, sp = swz_half<R>(tp) * SZ;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    R t[NR];
+                    __syncthreads();
+                    if (active) {
+#pragma unroll
+                        for (int e = 0; e < NR; ++e) {
+                            const uint32_t u = __builtin_amdgcn_readfirstlane(swz_half<R>(elem_poff<RB>(prev, e)) * SZ);
+                            *reinterpret_cast<R *>(lb + (sq ^ u)) = a[s][e].x;
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int e = 0; e < NR; ++e) {
+                        const uint32_t u = __builtin_amdgcn_readfirstlane(swz_half<R>(ep[e]) * SZ);
+                        t[e] = *reinterpret_cast<const R *>(lb + (sp ^ u));
+                    }
+                    __syncthreads();
+                    if (active) {
+#pragma unroll
+                        for (int e = 0; e < NR; ++e) {
+                            const uint32_t u = __builtin_amdgcn_readfirstlane(swz_half<R>(elem_poff<RB>(prev, e)) * SZ);
+                            *reinterpret_cast<R *>(lb + (sq ^ u)) = a[s][e].y;
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int e = 0; e < NR; ++e) {
+                        const uint32_t u = __builtin_amdgcn_readfirstlane(swz_half<R>(ep[e]) * SZ);
+                        a[s][e].x = t[e];
+                        a[s][e].y = *reinterpret_cast<const R *>(lb + (sp ^ u));
+                    }
+                }
+            } else {
             constexpr uint32_t SZ = sizeof(C);
             const uint32_t sq = swz<R>(thread_poff(prev, tb, tid)) * SZ, sp = swz<R>(tp) * SZ;
-            unsigned char *lb = reinterpret_cast<unsigned char *>(lds);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 __syncthreads();
@@ -597,6 +645,7 @@ __device__ __forceinline__ void tile_phases(const PassDesc &P, const PhaseDesc *
                     const uint32_t u = __builtin_amdgcn_readfirstlane(swz<R>(ep[e]) * SZ);
                     a[s][e] = *reinterpret_cast<const C *>(lb + (sp ^ u));
                 }
+            }
             }
         }
         // Each op reads one register set and writes the other, so that no op

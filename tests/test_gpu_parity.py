@@ -392,3 +392,34 @@ def test_lane_gates_match_oracle(qg, n, dtype):
             st.close()
     finally:
         qg.set_tuning("lane_gate", saved)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_half_lds_exchanges_are_bitwise_identical(qg, dtype):
+    """Multi-phase passes move the tile between register layouts through LDS either as whole
+    complex values or as real parts then imaginary parts: a permutation either way, so the
+    states (forward passes) and the adjoint gradients (two states per pass) agree bit for bit,
+    and match the oracle."""
+    n = 18
+    circ = W.config3(n, layers=6)
+    ref = oracle.simulate(circ)
+    _, npass = qg.plan_passes(circ, dtype, 1)
+    assert npass < circ.n_gates
+    train = W.config5(n=16, layers=4)
+    masks = W.zz_chain_masks(train.n_qubits)
+    coeffs = np.linspace(0.5, 1.5, masks.size)
+    key = f"half_lds_{dtype}"
+    saved = qg.get_tuning(key)
+    states, grads = [], []
+    try:
+        for h in (0, 1):
+            qg.set_tuning(key, h)
+            st = run(qg, circ, dtype, 1)
+            states.append(host(st))
+            st.close()
+            grads.append(qg.adjoint_grad(train, masks, coeffs, train.n_params, dtype)[1].cpu().numpy())
+    finally:
+        qg.set_tuning(key, saved)
+    assert np.max(np.abs(states[0] - ref)) < TOL[dtype]
+    assert np.array_equal(states[0], states[1])
+    assert np.array_equal(grads[0], grads[1])
