@@ -307,7 +307,8 @@ qg_status qg_get_tuning(const char *key, int64_t *value);
  * register bits, swizzle, XCD order) candidates and the fastest becomes that
  * target's entry (tuning keys tgt<q>_tile_<dt>, tgt<q>_reg_<dt>,
  * tgt<q>_swz_<dt>, tgt<q>_xcd_<dt>; tile 0 means "use the class"), used by
- * single-gate passes of one-qubit mixing gates. */
+ * single-gate passes of one-qubit mixing gates.  Targets whose single gates run
+ * on the lane kernel (lane_gate) are not timed and keep tile 0. */
 qg_status qg_autotune(qg_state *s, int reps, int32_t *table);
 
 /* Message describing the calling thread's last failed call ("" if none). */

@@ -309,6 +309,7 @@ PlanConfig batch_config(int n, bool c64) {
     cfg.max_gates_per_pass = n <= cfg.tile_bits ? (1 << 30) : 4096;
     cfg.use_classes = false;  // the persistent kernel is built for one register width
     cfg.diag_run_min = 0;     // its programs carry no fused diagonal runs
+    cfg.half_lds = false;     // its LDS is sized for whole complex values; registers limit occupancy
     clamp_config(&cfg);
     return cfg;
 }
@@ -1403,7 +1404,9 @@ qg_status qg_autotune(qg_state *s, int reps, int32_t *table) {
         const std::vector<Gate> gl{g};
         double best = 1e300;
         int keep[4] = {0, 0, 0, 0};
-        for (int k = 0; k < 6 && result == QG_OK; ++k) {
+        // Targets inside a cache line run on the lane kernel, whatever the tile shape.
+        const bool lane = (build_plan(gl, plan_config(n, c64, QG_FUSE_NONE)).passes[0].flags & PASS_LANE1) != 0;
+        for (int k = 0; k < 6 && result == QG_OK && !lane; ++k) {
             if (tc[k].tile > n) continue;
             int *e = tu.tgt[d][t];
             e[0] = tc[k].tile, e[1] = tc[k].reg, e[2] = tc[k].swz, e[3] = tc[k].xcd;

@@ -383,6 +383,7 @@ PlanConfig default_config(int n, bool c64, int fusion) {
     c.swz_bits = t.swz_bits;
     c.dense_min_gates = t.dense_min_gates;
     c.diag_run_min = t.diag_run_min;
+    c.half_lds = t.half_lds[d] != 0;
     return c;
 }
 
@@ -846,7 +847,7 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
         const int n_ops = prog.phases.back().op_end - prog.phases[pd.phase_begin].op_begin;
         if (!cfg.reverse && (tu.pipe == 2 || (tu.pipe == 1 && (pd.n_phase > 1 || n_ops >= tu.pipe_min_ops))))
             pd.flags |= PASS_PIPE;
-        if (pd.n_phase > 1 && tu.half_lds[cfg.c64 ? 1 : 0]) pd.flags |= PASS_HALFX;
+        if (pd.n_phase > 1 && cfg.half_lds) pd.flags |= PASS_HALFX;
         // Non-temporal state accesses only pay when every wavefront load/store
         // covers whole 128-byte lines: the first and last layouts must keep the
         // line-offset tile positions (3 for complex128, 4 for complex64) on lanes.

@@ -34,6 +34,7 @@ struct PlanConfig {
     int dense_min_gates = 1 << 30;  // a pass on <= 6 qubits with this many gates runs as a dense block
     bool use_classes = true;        // single-gate passes take their tile shape from the class table
     int diag_run_min = 3;           // consecutive diagonal ops fused into one (0: never)
+    bool half_lds = false;          // multi-phase passes exchange real and imaginary parts in turn
 };
 
 // Pass classes for tuning: by the highest qubit a pass needs in registers.
