@@ -144,6 +144,48 @@ def paper_shaped(qg, W, torch, n: int = 30):
     return {"n_qubits": n, **out}
 
 
+def large_shots(qg, W, torch, shots: int = 3000 << 15):
+    """Shot sampling at the paper's large shot counts (3000 * 2^m shots, m = 15): seeded
+    samples of a random product state at 15, 20 and 25 qubits (complex128), one call each."""
+    out = {"shots": shots}
+    for n in (15, 20, 25):
+        st = qg.State(n, "c128")
+        b = W.CircuitBuilder(n)
+        rng = W.SplitMix64(W.SEED_BASE + 40 + n)
+        for q in range(n):
+            b.g1(W.U3, q, *(2 * math.pi * rng.uniform(3)))
+        st.apply(b.build(), qg.FUSE_GREEDY)
+        st.sample(1000, 1)
+        ts = []
+        for r in range(3):
+            t, idx = timed(lambda: st.sample(shots, W.SEED_BASE + r), torch.cuda.synchronize)
+            del idx
+            ts.append(t)
+        t = float(np.median(ts))
+        out[f"n{n}"] = {"t_ms": round(t * 1e3, 2), "shots_per_s": shots / t}
+        st.close()
+        torch.cuda.empty_cache()
+    return out
+
+
+def precision_gap(qg, W, torch, n: int = 26):
+    """complex64 against complex128 on config 3's circuit shape (n qubits, 20 layers + QFT):
+    largest amplitude difference and the fidelity |<psi64|psi128>|^2, on the host."""
+    circ = W.config3(n, layers=20)
+    res = {}
+    for dt in ("c128", "c64"):
+        st = qg.State(n, dt)
+        st.apply(circ, qg.FUSE_GREEDY)
+        torch.cuda.synchronize()
+        res[dt] = st.tensor.cpu().numpy().astype(np.complex128)
+        st.close()
+    torch.cuda.empty_cache()
+    a, b = res["c128"], res["c64"]
+    return {"workload": f"config 3 shape, {n} qubits, 20 layers + QFT({n}), {circ.n_gates} gates",
+            "max_abs_diff": float(np.max(np.abs(a - b))), "max_abs_amplitude": float(np.max(np.abs(a))),
+            "fidelity_c64": float(abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real))}
+
+
 def adjoint_speedup(qg, W, torch):
     """Config 5: gradient of sum <Z_i Z_i+1> (24 qubits, 480 parameters) by one adjoint sweep
     vs the plain method, central differences (960 forward simulations + expectations)."""
@@ -385,6 +427,9 @@ def main():
         extras["config3"] = config3_timing(qg, W, torch)
         log("QFT and random CX-block unitaries (30 qubits c128)")
         extras["paper_shaped"] = paper_shaped(qg, W, torch)
+        log("large shot counts; complex64 vs complex128")
+        extras["large_shots"] = large_shots(qg, W, torch)
+        extras["precision"] = precision_gap(qg, W, torch)
         log("adjoint vs finite differences (config 5)")
         extras["adjoint"] = adjoint_speedup(qg, W, torch)
         log(f"adjoint speedup {extras['adjoint']['speedup']}x; batched vs plain loop (config 4)")

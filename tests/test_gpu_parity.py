@@ -423,3 +423,20 @@ def test_half_lds_exchanges_are_bitwise_identical(qg, dtype):
     assert np.max(np.abs(states[0] - ref)) < TOL[dtype]
     assert np.array_equal(states[0], states[1])
     assert np.array_equal(grads[0], grads[1])
+
+
+def test_large_shot_counts(qg):
+    """3000 * 2^12 shots (the paper's 3000 * 2^m shot rule) from one call: every index is in
+    range and the counts pass the chi-square test against the oracle's probabilities; a
+    prefix of the shots equals the oracle's draws for the same Philox counters."""
+    n = 12
+    shots = 3000 << n
+    circ = prep_layer(n, 77)
+    psi = oracle.simulate(circ)
+    st = run(qg, circ, "c128", 1)
+    idx = st.sample(shots, 1234).cpu().numpy().astype(np.uint64)
+    st.close()
+    assert idx.size == shots and int(idx.max()) < (1 << n)
+    counts = np.bincount(idx.astype(np.int64), minlength=1 << n)
+    assert chi_square_p(counts, np.abs(psi) ** 2, shots) > 0.01
+    assert np.mean(idx[:10000] == oracle.sample(psi, 10000, 1234)) >= 0.999
