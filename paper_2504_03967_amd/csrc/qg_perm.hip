@@ -1,4 +1,6 @@
-// qg_perm.hip -- SWAP of two qubits as a pure permutation.
+// qg_perm.hip -- standalone single-gate kernels outside the tile pass: SWAP of
+// two qubits as a pure permutation, and one-qubit gates or CX whose target lies
+// inside a cache line as a cross-lane exchange.
 //
 // k_swap2: only the amplitudes whose two bits differ move (half the state),
 // each exchanged with its partner.  Used for a standalone SWAP whose lower
