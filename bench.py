@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2504_03967_amd/csrc/qg_tile_dev.h", "paper_2504_03967_amd/csrc/qg_tile.hip",
                   "paper_2504_03967_amd/csrc/qg_plan.cpp", "paper_2504_03967_amd/csrc/qg_internal.h",
                   "paper_2504_03967_amd/csrc/qg_api.cpp")
-MEASURED_TRAFFIC = {"sources": "4e9e9f26221ea8a1", "traffic_over_algorithmic": 1.00062}
+MEASURED_TRAFFIC = {"sources": "066cae024e0531af", "traffic_over_algorithmic": 1.00062}
 
 
 def kernel_sources_hash() -> str:
