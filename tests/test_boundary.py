@@ -141,3 +141,25 @@ def test_plan_kernels_pick_the_permutation_and_lane_kernels(qg, dtype, line_bits
     assert set(qg.plan_kernels(W.random_circuit(10, 50, seed=3), dtype, qg.FUSE_NONE)) == {"tile"}
     circ = W.config3(26, layers=5)
     assert len(qg.plan_kernels(circ, dtype, qg.FUSE_GREEDY)) == qg.plan_passes(circ, dtype, qg.FUSE_GREEDY)[1]
+
+
+def test_plan_kernels_validates_and_reports_counts(qg):
+    """qg_plan_kernels rejects what qg_plan_passes rejects, and a bad fusion mode or a negative
+    capacity; with capacity 0 it only counts; an empty circuit has no passes."""
+    import ctypes
+    bad = W.CircuitBuilder(4).g2(W.CX, 2, 2).build()
+    with pytest.raises(qg.QGError) as e:
+        qg.plan_kernels(bad)
+    assert e.value.status == qg.QG_EINVAL
+    circ = W.random_circuit(14, 40, seed=5)
+    ca = qg.CircuitArgs(circ)
+    n = ctypes.c_int32(-1)
+    assert qg.lib.qg_plan_kernels(ca.ptr, qg.C128, 7, None, 0, ctypes.byref(n)) == qg.QG_EINVAL
+    assert qg.lib.qg_plan_kernels(ca.ptr, qg.C128, qg.FUSE_NONE, None, -1, ctypes.byref(n)) == qg.QG_EINVAL
+    assert qg.lib.qg_plan_kernels(ca.ptr, qg.C128, qg.FUSE_NONE, None, 0, ctypes.byref(n)) == qg.QG_OK
+    assert n.value == circ.n_gates
+    k = np.full(3, -7, dtype=np.int32)
+    assert qg.lib.qg_plan_kernels(ca.ptr, qg.C128, qg.FUSE_NONE, k.ctypes.data, 2, ctypes.byref(n)) == qg.QG_OK
+    assert k[2] == -7 and set(k[:2]) <= set(range(len(qg.KERNEL_NAMES)))
+    empty = W.Circuit(14, np.zeros((0, 3), np.int32), np.zeros((0, 3)), np.zeros(0, np.int32))
+    assert qg.plan_kernels(empty) == []
