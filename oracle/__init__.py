@@ -53,6 +53,8 @@ def _load():
         lib.qgo_adjoint_grad.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P, ctypes.c_int,
                                          ctypes.c_int, P, P, P, P]
         lib.qgo_adjoint_grad.restype = ctypes.c_int
+        lib.qgo_batch_zz_chain.argtypes = [ctypes.c_int, P, P, P, P, P]
+        lib.qgo_batch_zz_chain.restype = ctypes.c_int
         lib.qgo_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -129,6 +131,20 @@ def sample(psi: np.ndarray, shots: int, seed: int) -> np.ndarray:
     out = np.empty(shots, dtype=np.uint64)
     if _load().qgo_sample(n, _ptr(psi), shots, seed, _ptr(out)) != 0:
         raise MemoryError("oracle: sample allocation failed")
+    return out
+
+
+def batch_zz_chain(circs) -> np.ndarray:
+    """sum_q <Z_q Z_{q+1}> of each circuit's final state (independent circuits in parallel)."""
+    n = np.array([c.n_qubits for c in circs], dtype=np.int32)
+    goff = np.zeros(len(circs) + 1, dtype=np.int64)
+    goff[1:] = np.cumsum([c.n_gates for c in circs])
+    gt = np.ascontiguousarray(np.concatenate([_gates(c)[0] for c in circs]), dtype=np.int32)
+    gp = np.ascontiguousarray(np.concatenate([_gates(c)[1] for c in circs]), dtype=np.float64)
+    out = np.empty(len(circs), dtype=np.float64)
+    rc = _load().qgo_batch_zz_chain(len(circs), _ptr(n), _ptr(goff), _ptr(gt), _ptr(gp), _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle: batch failed ({rc})")
     return out
 
 

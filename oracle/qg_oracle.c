@@ -362,6 +362,45 @@ int qgo_adjoint_grad(int n, int64_t n_gates, const int32_t *gate_type, const dou
     return 0;
 }
 
+/* Independent circuits, as in the parallel ("batched") mode of Sec. 2.4: circuit c has
+ * n[c] qubits and the gate rows [goff[c], goff[c + 1]) of gate_type / gate_param; each
+ * starts from |0...0> and out[c] is the open-chain observable sum_{q < n-1} <Z_q Z_{q+1}>
+ * of its final state.  One circuit per OpenMP thread at a time; the gate loops inside run
+ * on that thread alone (the nested parallel regions are inactive).  Returns 0, -1 - c for
+ * the first circuit c holding a malformed gate, or -(1 << 30) when a state cannot be
+ * allocated. */
+int qgo_batch_zz_chain(int n_circ, const int32_t *n, const int64_t *goff, const int32_t *gate_type,
+                       const double *gate_param, double *out)
+{
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < n_circ; c++) {
+        int nq = n[c];
+        cplx *psi = malloc(sizeof(cplx) << nq);
+        if (!psi) {
+#pragma omp critical
+            err = -(1 << 30);
+            continue;
+        }
+        qgo_init(nq, psi);
+        if (qgo_apply_circuit(nq, psi, goff[c + 1] - goff[c], gate_type + 3 * goff[c],
+                              gate_param + 3 * goff[c])) {
+#pragma omp critical
+            if (err == 0 || -1 - c > err) err = -1 - c;
+        }
+        double sum = 0;
+        for (int q = 0; q + 1 < nq; q++) {
+            uint64_t m = 3ull << q;
+            double t;
+            qgo_expval(nq, psi, 1, &m, &t);
+            sum += t;
+        }
+        out[c] = sum;
+        free(psi);
+    }
+    return err;
+}
+
 /* Number of OpenMP threads a parallel region of the oracle uses. */
 int qgo_num_threads(void)
 {

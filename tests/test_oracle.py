@@ -249,6 +249,33 @@ def test_expval_pins():
         assert abs(oracle.expval(psi, [m])[0] - np.vdot(psi, Zm @ psi).real) < 1e-14
 
 
+def test_batch_zz_chain_closed_forms():
+    """The oracle's batched entry (independent circuits side by side) on circuits whose open-
+    chain sum_q <Z_q Z_{q+1}> is known in closed form: GHZ (every term 1), basis states
+    (term q is (-1)^{x_q xor x_{q+1}}), the uniform superposition (every term 0), and a dense
+    Z Z operator on a random 4-qubit circuit."""
+    circs, expect = [], []
+    for n in (1, 2, 7, 12):
+        circs.append(W.ghz(n))
+        expect.append(n - 1)
+    for n, x in ((5, 0b10110), (9, 0b101010101), (3, 0b111)):
+        b = W.CircuitBuilder(n)
+        for q in range(n):
+            if (x >> q) & 1:
+                b.g1(W.X, q)
+        circs.append(b.build())
+        expect.append(sum((-1) ** (((x >> q) ^ (x >> (q + 1))) & 1) for q in range(n - 1)))
+    circs.append(W.uniform_superposition(10))
+    expect.append(0.0)
+    r = W.random_circuit(4, 60, seed=8)
+    psi = dense_circuit(r)[:, 0]
+    zz = sum(kron_op(4, {q: PZ, q + 1: PZ}) for q in range(3))
+    circs.append(r)
+    expect.append(np.vdot(psi, zz @ psi).real)
+    got = oracle.batch_zz_chain(circs)
+    assert np.max(np.abs(got - np.array(expect, float))) < 1e-13
+
+
 # --------------------------------------------------------------- sampling
 
 def test_philox_known_answer_vectors():
