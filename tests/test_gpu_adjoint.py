@@ -49,9 +49,12 @@ def test_adjoint_matches_oracle_adjoint(qg, n, dtype):
     coeffs = np.linspace(0.5, 1.5, masks.size)
     val, grad = qg.adjoint_grad(circ, masks, coeffs, npar, dtype)
     rv, rg = oracle.adjoint_grad(circ, npar, masks, coeffs)
-    tol = 1e-10 if dtype == "c128" else 2e-4
-    assert abs(val.item() - rv) < tol
-    assert np.max(np.abs(grad.cpu().numpy() - rg)) < tol
+    # per Z-string term tolerance (1e-12 / 1e-5), times sum |coeff| for the weighted sum; a
+    # gradient Im<lambda|P|psi> with lambda = sum_m c_m Z_m psi is such a sum as well.  The
+    # complex128 gradients are held to the adjoint's 1e-10.
+    w = float(np.sum(np.abs(coeffs)))
+    assert abs(val.item() - rv) < (1e-12 if dtype == "c128" else 1e-5) * w
+    assert np.max(np.abs(grad.cpu().numpy() - rg)) < (1e-10 if dtype == "c128" else 1e-5 * w)
 
 
 def test_config5_adjoint_vs_parameter_shift_and_fd(qg):
@@ -68,7 +71,7 @@ def test_config5_adjoint_vs_parameter_shift_and_fd(qg):
         st.apply(c, qg.FUSE_GREEDY)
         return float(st.expval(masks, coeffs)[1])
 
-    assert abs(val.item() - f(circ)) < 1e-10
+    assert abs(val.item() - f(circ)) < 1e-12 * (n - 1)
     pick = W.SplitMix64(5).below(npar, 8)
     for k in pick:
         (g,) = np.nonzero(circ.param_idx == k)
@@ -92,7 +95,7 @@ def test_config5_adjoint_vs_oracle_sampled(qg):
     coeffs = np.ones(23)
     val, grad = qg.adjoint_grad(circ, masks, coeffs, 480, "c128")
     rv, rg = oracle.adjoint_grad(circ, 480, masks, coeffs)
-    assert abs(val.item() - rv) < 1e-10
+    assert abs(val.item() - rv) < 1e-12 * 23
     assert np.max(np.abs(grad.cpu().numpy() - rg)) < 1e-10
 
 

@@ -3,6 +3,7 @@ hold at any size — norm conservation, mirror circuits, the QFT closed form on 
 GHZ, Porter-Thomas statistics of random circuits and of their shots — and the benchmark's
 own sweep on sampled amplitudes the oracle computes from a factorised state."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -14,6 +15,7 @@ from paper_2504_03967_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 CASES = [(31, "c128"), (32, "c64")]
+GOLDEN_C3 = os.path.join(os.path.dirname(__file__), "golden", "config3_31q_oracle.txt")
 TOL = {"c128": 1e-12, "c64": 1e-5}
 
 
@@ -47,6 +49,51 @@ def test_config3_norm_porter_thomas_and_shots(qg, n, dtype):
     shots = st.sample(20000, W.SEED_BASE + 2).cpu().numpy().astype(np.uint64)
     ps = st.probs(shots).cpu().numpy() * N
     assert np.all(ps > 0) and abs(ps.mean() - 2) < 0.15
+    st.close()
+
+
+def load_config3_golden(path):
+    """(norm, <Z_0 Z_{n-1}>, indices, amplitudes) written by tests/golden/make_config3_golden.py."""
+    norm = zz = None
+    idx, amp = [], []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, *v = line.split()
+            if k == "norm":
+                norm = float(v[0])
+            elif k.startswith("zz_"):
+                zz = float(v[0])
+            else:
+                idx.append(int(k))
+                amp.append(complex(float(v[0]), float(v[1])))
+    return norm, zz, np.array(idx, dtype=np.uint64), np.array(amp)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_config3_31q_outputs_against_oracle(qg, dtype):
+    """The large-circuit workload at its complex128 size (31 qubits, 5111 gates): the 1024
+    seeded amplitudes and probabilities, <Z_0 Z_30> and the norm against the FP64 oracle's
+    values for the same gate list (stored: the oracle needs a 32 GiB state and ~1.1e13
+    amplitude updates).  complex64 runs the same 31-qubit circuit; its configured 32-qubit
+    size would need a 64 GiB FP64 oracle state."""
+    n = 31
+    if not os.path.exists(GOLDEN_C3):
+        pytest.skip("oracle outputs not generated (tests/golden/make_config3_golden.py)")
+    norm, zz, idx, amp = load_config3_golden(GOLDEN_C3)
+    assert np.array_equal(idx, W.config3_indices(n))
+    st = qg.State(n, dtype)
+    st.apply(W.config3(n), qg.FUSE_GREEDY)
+    got = st.tensor[torch.as_tensor(idx.astype(np.int64), device="cuda")].cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(got - amp)) < TOL[dtype]
+    p = st.probs(idx).cpu().numpy()
+    pref = np.abs(amp) ** 2
+    assert np.max(np.abs(p - pref)) / pref.mean() < (1e-10 if dtype == "c128" else 1e-4)
+    terms, _ = st.expval([0, 1 | (1 << (n - 1))])
+    t = terms.cpu().numpy()
+    assert abs(t[0] - norm) < (1e-13 if dtype == "c128" else 1e-5)
+    assert abs(t[1] - zz) < TOL[dtype]
     st.close()
 
 

@@ -80,7 +80,7 @@ def test_every_op_at_every_position(qg, n, dtype):
         for fusion in (0, 1):
             got = host(run(qg, circ, dtype, fusion))
             err = np.max(np.abs(got - ref))
-            assert err < TOL[dtype] * max(1, circ.n_gates / 200), (op, fusion, err)
+            assert err < TOL[dtype], (op, fusion, err)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -143,34 +143,61 @@ def test_config2_qcrank_closed_form_and_shots(qg, dtype):
         assert np.all(np.abs(z) < 5.5)
 
 
+@pytest.fixture(scope="module")
+def config3_26q():
+    n = 26
+    circ = W.config3(n)
+    return circ, oracle.simulate(circ)
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_config3_shape_reduced(qg, dtype):
-    n = 20
-    circ = W.config3(n, layers=20)
+def test_config3_full_depth_every_amplitude(qg, config3_26q, dtype):
+    """The large-circuit workload at full depth (100 random U3 + CX layers, then the exact
+    QFT, 4264 gates) on 26 qubits, greedy fusion as at full size (deep multi-layout tile
+    passes, fused diagonal runs, standalone SWAPs): every amplitude against the oracle, the
+    whole-state 2-norm of the error, the 1024 seeded probabilities and <Z_0 Z_25>."""
+    circ, psi = config3_26q
+    n = circ.n_qubits
+    kinds = qg.plan_kernels(circ, dtype, qg.FUSE_GREEDY)
+    passes = qg.plan_passes(circ, dtype, qg.FUSE_GREEDY)[1]
+    assert kinds.count("tile") > 100 and passes < circ.n_gates / 10
     st = run(qg, circ, dtype, 1)
-    psi = oracle.simulate(circ)
+    got = host(st)
+    err = np.abs(got - psi)
+    assert err.max() < TOL[dtype], float(err.max())
+    assert np.linalg.norm(got - psi) < TOL[dtype], float(np.linalg.norm(got - psi))
     idx = W.config3_indices(n)
     p = st.probs(idx).cpu().numpy()
-    assert np.max(np.abs(p - np.abs(psi[idx.astype(np.int64)]) ** 2)) < TOL[dtype]
+    pref = np.abs(psi[idx.astype(np.int64)]) ** 2
+    # probabilities are ~2^-26: compare them on their own scale as well
+    assert np.max(np.abs(p - pref)) / pref.mean() < (1e-10 if dtype == "c128" else 1e-4)
     masks = np.array([0, (1 << 0) | (1 << (n - 1))], dtype=np.uint64)
     terms, _ = st.expval(masks)
     ref = oracle.expval(psi, masks)
     assert np.max(np.abs(terms.cpu().numpy() - ref)) < TOL[dtype]
     assert abs(terms[0].item() - 1) < (1e-13 if dtype == "c128" else 1e-5)
+    st.close()
 
 
-def test_expval_many_terms_and_weights(qg):
-    n = 14
-    circ = W.random_circuit(n, 200, seed=3)
+@pytest.mark.parametrize("n", [3, 9, 14, 23])
+def test_expval_many_terms_and_weights(qg, n):
+    """Up to 64 masks share one read of the state; 150 masks take three reads.  Masks with
+    bits only in the thread part (index bits 0..7), only in the row part (8..11), only above,
+    and random ones; states smaller than one 4096-amplitude group as well."""
+    circ = W.random_circuit(n, 200, seed=3 + n)
     st = run(qg, circ)
     psi = oracle.simulate(circ)
-    rng = np.random.default_rng(0)
-    masks = rng.integers(0, 1 << n, 41).astype(np.uint64)
-    coeffs = rng.normal(size=41)
-    terms, total = st.expval(masks, coeffs)
-    ref = oracle.expval(psi, masks)
-    assert np.max(np.abs(terms.cpu().numpy() - ref)) < 1e-12
-    assert abs(float(total) - np.dot(coeffs, ref)) < 1e-11
+    rng = np.random.default_rng(n)
+    full = (1 << n) - 1
+    fixed = [0, full, 0xFF & full, 0xF00 & full, full & ~0xFFF, 1 << (n - 1), 0x101 & full]
+    masks = np.concatenate([np.array(fixed, dtype=np.uint64),
+                            rng.integers(0, 1 << n, 150 - len(fixed)).astype(np.uint64)])
+    coeffs = rng.normal(size=masks.size)
+    for k in (1, 3, 16, 41, 64, 65, 150):
+        terms, total = st.expval(masks[:k], coeffs[:k])
+        ref = oracle.expval(psi, masks[:k])
+        assert np.max(np.abs(terms.cpu().numpy() - ref)) < 1e-12, k
+        assert abs(float(total) - np.dot(coeffs[:k], ref)) < 1e-12 * np.sum(np.abs(coeffs[:k])), k
 
 
 def test_probs_index_list_ragged(qg):
