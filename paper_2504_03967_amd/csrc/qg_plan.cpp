@@ -534,6 +534,28 @@ std::vector<PassRange> fuse(const std::vector<Gate> &g, const PlanConfig &cfg) {
     return out;
 }
 
+// Runs of consecutive gates (in the given order) that touch at most 6 qubits and
+// hold at least dense_min_gates gates: each becomes a pass of its own, which the
+// plan then executes as one dense block.  Greedy from the left, longest run
+// from each start.  Empty when dense blocks are off.
+std::vector<PassRange> dense_runs(const std::vector<Gate> &g, const PlanConfig &cfg) {
+    std::vector<PassRange> runs;
+    const int G = (int)g.size();
+    if (cfg.reverse || cfg.n < 8 || cfg.dense_min_gates >= (1 << 30) || cfg.fusion == QG_FUSE_NONE) return runs;
+    for (int i = 0; i < G;) {
+        uint64_t q = 0;
+        int j = i;
+        while (j < G && popcount64(q | touched_qubits(g[j])) <= 6) q |= touched_qubits(g[j++]);
+        if (j - i >= cfg.dense_min_gates && dense_block_qubits(g, i, j, cfg.n)) {
+            runs.push_back({i, j});
+            i = j;
+        } else {
+            ++i;
+        }
+    }
+    return runs;
+}
+
 Schedule schedule(const std::vector<Gate> &g, const PlanConfig &cfg) {
     Schedule sc;
     const int G = (int)g.size();
@@ -547,34 +569,47 @@ Schedule schedule(const std::vector<Gate> &g, const PlanConfig &cfg) {
     const int low = n <= b ? n : std::min(cfg.low_bits, b);
     const uint64_t low_mask = low >= 64 ? ~0ull : ((1ull << low) - 1);
     const int max_high = n <= b ? 64 : std::min(cfg.max_high, b - low);
-    std::vector<int> pending(G);
-    for (int i = 0; i < G; ++i) pending[i] = i;
     const int kMaxGradPerPass = 64;  // bounds the adjoint partial-sum scratch
-    while (!pending.empty()) {
-        uint64_t high = 0, blocked = 0;
-        int taken = 0, grads = 0;
-        std::vector<int> rest;
-        rest.reserve(pending.size());
-        const int begin = (int)sc.order.size();
-        for (int idx : pending) {
-            const Gate &x = g[idx];
-            const uint64_t touch = touched_qubits(x);
-            const uint64_t req = required_qubits(x) & ~low_mask;
-            const bool ready = (touch & blocked) == 0;
-            const int gr = (cfg.reverse && x.pidx >= 0) ? 1 : 0;
-            if (ready && taken < cfg.max_gates_per_pass && grads + gr <= kMaxGradPerPass &&
-                popcount64(high | req) <= max_high) {
-                high |= req;
-                sc.order.push_back(idx);
-                ++taken;
-                grads += gr;
-            } else {
-                blocked |= touch;
-                rest.push_back(idx);
+    // Gates between dense runs are scheduled greedily among themselves; a dense
+    // run keeps its gates in order as one pass, and nothing moves across it.
+    std::vector<PassRange> runs = dense_runs(g, cfg);
+    runs.push_back({G, G});
+    int seg = 0;
+    for (const PassRange &dr : runs) {
+        std::vector<int> pending;
+        for (int i = seg; i < dr.g_begin; ++i) pending.push_back(i);
+        while (!pending.empty()) {
+            uint64_t high = 0, blocked = 0;
+            int taken = 0, grads = 0;
+            std::vector<int> rest;
+            rest.reserve(pending.size());
+            const int begin = (int)sc.order.size();
+            for (int idx : pending) {
+                const Gate &x = g[idx];
+                const uint64_t touch = touched_qubits(x);
+                const uint64_t req = required_qubits(x) & ~low_mask;
+                const bool ready = (touch & blocked) == 0;
+                const int gr = (cfg.reverse && x.pidx >= 0) ? 1 : 0;
+                if (ready && taken < cfg.max_gates_per_pass && grads + gr <= kMaxGradPerPass &&
+                    popcount64(high | req) <= max_high) {
+                    high |= req;
+                    sc.order.push_back(idx);
+                    ++taken;
+                    grads += gr;
+                } else {
+                    blocked |= touch;
+                    rest.push_back(idx);
+                }
             }
+            sc.ranges.push_back({begin, (int)sc.order.size()});
+            pending.swap(rest);
         }
-        sc.ranges.push_back({begin, (int)sc.order.size()});
-        pending.swap(rest);
+        if (dr.g_end > dr.g_begin) {
+            const int begin = (int)sc.order.size();
+            for (int i = dr.g_begin; i < dr.g_end; ++i) sc.order.push_back(i);
+            sc.ranges.push_back({begin, (int)sc.order.size()});
+        }
+        seg = dr.g_end;
     }
     return sc;
 }

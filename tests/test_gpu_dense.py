@@ -46,6 +46,8 @@ def local_circuit(n, k, n_gates, seed):
 @pytest.mark.parametrize("n,k", [(10, 4), (12, 5), (13, 6), (16, 3), (18, 5), (20, 6), (21, 2)])
 def test_dense_block_matches_oracle(qg_dense, n, k, dtype):
     prep, circ = local_circuit(n, k, 40, seed=100 * n + k)
+    kinds = qg_dense.plan_kernels(circ, dtype, qg_dense.FUSE_GREEDY)
+    assert kinds and all(x == "dense" for x in kinds), kinds
     st = qg_dense.State(n, dtype)
     st.apply(prep, qg_dense.FUSE_NONE)      # generic start state
     st.apply(circ, qg_dense.FUSE_GREEDY)    # one pass on <= 6 qubits -> dense block
@@ -57,8 +59,15 @@ def test_dense_block_matches_oracle(qg_dense, n, k, dtype):
 
 
 def test_dense_in_a_full_circuit(qg_dense):
-    circ = W.config3(18, layers=6)
-    st = qg_dense.State(18, "c128")
+    """Dense blocks between tile passes: random layers, a run of 40 gates on 5 qubits, a run
+    of 30 gates on 6 qubits, random layers again."""
+    n = 18
+    circ = W.concat(W.concat(W.config3(n, layers=3, with_qft=False), local_circuit(n, 5, 40, seed=7)[1]),
+                    W.concat(local_circuit(n, 6, 30, seed=8)[1], W.config3(n, seed=5, layers=3)))
+    qg_dense.set_tuning("dense_min_gates", 20)  # the two local runs, not the random layers
+    kinds = qg_dense.plan_kernels(circ, "c128", qg_dense.FUSE_GREEDY)
+    assert kinds.count("dense") >= 2 and "tile" in kinds, kinds
+    st = qg_dense.State(n, "c128")
     st.apply(circ, qg_dense.FUSE_GREEDY)
     torch.cuda.synchronize()
     assert np.max(np.abs(st.tensor.cpu().numpy() - oracle.simulate(circ))) < 1e-12
