@@ -18,6 +18,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -286,6 +287,25 @@ def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -413,7 +433,7 @@ def main():
         log(f"oracle sample: {sample.n_gates} gates in {dt:.1f} s on {threads} threads")
         del psi
         cpu = {"value": sample.n_gates * (1 << n) / dt, "unit": "amp-updates/s", "cores": threads,
-               "kind": "oracle",
+               "kind": "oracle", "nproc": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(),
                "sample": f"first {sample.n_gates} gates of the {n}-qubit sweep on a 2^{n} complex128 state "
                          f"(one FP64 pass per gate), {dt:.1f} s"}
 

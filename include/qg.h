@@ -137,7 +137,11 @@ qg_status qg_probs(qg_state *s, const uint64_t *idx, int64_t n_idx, double *out)
 qg_status qg_sample(qg_state *s, int64_t shots, uint64_t seed, uint64_t *out_idx);
 
 /* Pauli-Z-string expectations <Z_m> = sum_i p_i (-1)^{popcount(i & zmask[m])}
- * for n_terms host masks (each < 2^n), accumulated in FP64.  out_terms: device
+ * for n_terms host masks (each < 2^n), accumulated in FP64.  Not an operation
+ * of the paper, which reports shot counts only: it is the observable of the
+ * workloads this library serves (sums of Z_i Z_j terms), evaluated from the
+ * probabilities p_i = |alpha_i|^2 of App. A's state vector.  One read of the
+ * state serves up to 64 masks.  out_terms: device
  * [n_terms] or NULL; out_sum: device scalar sum_m coeff[m] <Z_m> or NULL
  * (coeff may be NULL only when out_sum is NULL).  n_terms >= 0. */
 qg_status qg_expval(qg_state *s, const uint64_t *zmask, const double *coeff, int n_terms,

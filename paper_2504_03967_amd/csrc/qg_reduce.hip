@@ -65,71 +65,81 @@ __global__ void k_probs(const typename V2<R>::T *__restrict__ psi, uint64_t dim,
 
 // ---------------------------------------------------------------- expval
 
-constexpr int kTermsPerPass = 16;
+// Masks evaluated per read of the state (1, 4, 16 or 64 at a time).
+constexpr int kTermsPerPass = 64;
+// A group is 16 x kThreads consecutive amplitudes: thread t holds index bits
+// 0..7 = t and 16 rows j (index bits 8..11); the bits above are uniform over
+// the block.
+constexpr int kGroupRows = 16;
+constexpr uint64_t kGroup = (uint64_t)kGroupRows * kThreads;
 
 inline int expval_blocks(uint64_t dim) {
-    uint64_t b = dim / (kThreads * 16);
+    uint64_t b = dim / kGroup;
     if (b < 1) b = 1;
     if (b > 1024) b = 1024;
     return (int)b;
 }
 
-// Each block reduces a contiguous chunk.  Per term the thread accumulates the
-// probability mass of odd parity; <Z_m> = total - 2 odd_m.  Indices below 2^32
-// use 32-bit parity arithmetic (IDX = uint32_t).
-template <typename R, int TM, typename IDX>
+// <Z_m> restricted to a block's chunk, for TM masks per read.  With i = g | j << 8 | t
+// (g the group's high bits), (-1)^{popcount(i & m)} factors into a thread sign
+// (bits 0..7), a row sign (bits 8..11) and a group sign.  Per group each thread
+// takes the Walsh-Hadamard transform W_k = sum_j (-1)^{popcount(j & k)} p_j of
+// its 16 probabilities; mask m then adds (group sign) * W_{(m >> 8) & 15}, with
+// a uniform index into the thread's registers.  The thread sign is applied once
+// at the end.  So the work per amplitude no longer grows with the mask count.
+template <typename R, int TM>
 __global__ void __launch_bounds__(kThreads)
 k_expval_part(const typename V2<R>::T *__restrict__ psi, uint64_t dim, const uint64_t *__restrict__ masks,
               int n_terms, int term0, double *__restrict__ part, int nblocks) {
-    using C = typename V2<R>::T;
-    constexpr int U = 4;
-    __shared__ double red[TM + 1][kThreads / 64];
-    IDX mk[TM];
+    __shared__ double red[TM][kThreads / 64];
+    const uint32_t tid = threadIdx.x;
+    double acc[TM];
 #pragma unroll
-    for (int t = 0; t < TM; ++t) mk[t] = term0 + t < n_terms ? (IDX)masks[term0 + t] : (IDX)0;
-    double odd[TM], total = 0.0;
-#pragma unroll
-    for (int t = 0; t < TM; ++t) odd[t] = 0.0;
+    for (int t = 0; t < TM; ++t) acc[t] = 0.0;
     const uint64_t chunk = (dim + nblocks - 1) / nblocks;
     const uint64_t lo = blockIdx.x * chunk;
     const uint64_t hi = lo + chunk < dim ? lo + chunk : dim;
-    uint64_t i = lo + threadIdx.x;
-    for (; i + (U - 1) * kThreads < hi; i += U * kThreads) {
-        C v[U];
+    for (uint64_t g = lo; g < hi; g += kGroup) {
+        double w[kGroupRows];
+        if (g + kGroup <= hi) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = psi[i + u * kThreads];
+            for (int j = 0; j < kGroupRows; ++j) w[j] = prob(psi[g + j * kThreads + tid]);
+        } else {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double p = prob(v[u]);
-            const IDX ii = (IDX)(i + u * kThreads);
-            total += p;
+            for (int j = 0; j < kGroupRows; ++j) {
+                const uint64_t i = g + j * kThreads + tid;
+                w[j] = i < hi ? prob(psi[i]) : 0.0;
+            }
+        }
 #pragma unroll
-            for (int t = 0; t < TM; ++t) odd[t] += (popc(ii & mk[t]) & 1) ? p : 0.0;
+        for (int s = 1; s < kGroupRows; s <<= 1)
+#pragma unroll
+            for (int j = 0; j < kGroupRows; ++j)
+                if (!(j & s)) {
+                    const double a = w[j], b = w[j | s];
+                    w[j] = a + b;
+                    w[j | s] = a - b;
+                }
+        const uint64_t gh = g >> 12;
+#pragma unroll
+        for (int t = 0; t < TM; ++t) {
+            const uint64_t m = term0 + t < n_terms ? masks[term0 + t] : 0ull;
+            const double v = w[(m >> 8) & (kGroupRows - 1)];
+            acc[t] += (__popcll(gh & (m >> 12)) & 1) ? -v : v;
         }
     }
-    for (; i < hi; i += kThreads) {
-        const double p = prob(psi[i]);
-        const IDX ii = (IDX)i;
-        total += p;
-#pragma unroll
-        for (int t = 0; t < TM; ++t) odd[t] += (popc(ii & mk[t]) & 1) ? p : 0.0;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const double tw = wave_sum(total);
-    if (lane == 0) red[TM][wave] = tw;
+    const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
-        const double v = wave_sum(odd[t]);
+        const uint64_t m = term0 + t < n_terms ? masks[term0 + t] : 0ull;
+        const double v = wave_sum((__popc(tid & (uint32_t)m & 0xffu) & 1) ? -acc[t] : acc[t]);
         if (lane == 0) red[t][wave] = v;
     }
     __syncthreads();
-    if (threadIdx.x < TM && term0 + (int)threadIdx.x < n_terms) {
-        double so = 0.0, st = 0.0;
-        for (int w = 0; w < kThreads / 64; ++w) {
-            so += red[threadIdx.x][w];
-            st += red[TM][w];
-        }
-        part[(int64_t)(term0 + threadIdx.x) * nblocks + blockIdx.x] = st - 2.0 * so;
+    if (tid < TM && term0 + (int)tid < n_terms) {
+        double so = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) so += red[tid][w];
+        part[(int64_t)(term0 + tid) * nblocks + blockIdx.x] = so;
     }
 }
 
@@ -346,26 +356,20 @@ hipError_t launch_expval(bool c64, const void *psi, uint64_t dim, const uint64_t
                          int n_terms, double *part, double *out_terms, double *out_sum, hipStream_t st) {
     if (n_terms <= 0) return hipSuccess;
     const int nb = expval_blocks(dim);
-    const bool w64 = dim > (1ull << 32);
 #define QG_EXPVAL_LAUNCH(TM)                                                                                      \
     do {                                                                                                          \
-        if (c64 && w64)                                                                                           \
-            hipLaunchKernelGGL((k_expval_part<float, TM, uint64_t>), dim3(nb), dim3(kThreads), 0, st,              \
-                               (const float2 *)psi, dim, masks, n_terms, t0, part, nb);                           \
-        else if (c64)                                                                                             \
-            hipLaunchKernelGGL((k_expval_part<float, TM, uint32_t>), dim3(nb), dim3(kThreads), 0, st,              \
-                               (const float2 *)psi, dim, masks, n_terms, t0, part, nb);                           \
-        else if (w64)                                                                                             \
-            hipLaunchKernelGGL((k_expval_part<double, TM, uint64_t>), dim3(nb), dim3(kThreads), 0, st,             \
-                               (const double2 *)psi, dim, masks, n_terms, t0, part, nb);                          \
+        if (c64)                                                                                                  \
+            hipLaunchKernelGGL((k_expval_part<float, TM>), dim3(nb), dim3(kThreads), 0, st, (const float2 *)psi,   \
+                               dim, masks, n_terms, t0, part, nb);                                                \
         else                                                                                                      \
-            hipLaunchKernelGGL((k_expval_part<double, TM, uint32_t>), dim3(nb), dim3(kThreads), 0, st,             \
-                               (const double2 *)psi, dim, masks, n_terms, t0, part, nb);                          \
+            hipLaunchKernelGGL((k_expval_part<double, TM>), dim3(nb), dim3(kThreads), 0, st, (const double2 *)psi, \
+                               dim, masks, n_terms, t0, part, nb);                                                \
     } while (0)
     for (int t0 = 0; t0 < n_terms; t0 += kTermsPerPass) {
         const int left = n_terms - t0;
         if (left <= 1) QG_EXPVAL_LAUNCH(1);
         else if (left <= 4) QG_EXPVAL_LAUNCH(4);
+        else if (left <= 16) QG_EXPVAL_LAUNCH(16);
         else QG_EXPVAL_LAUNCH(kTermsPerPass);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
