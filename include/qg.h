@@ -147,6 +147,23 @@ qg_status qg_sample(qg_state *s, int64_t shots, uint64_t seed, uint64_t *out_idx
 qg_status qg_expval(qg_state *s, const uint64_t *zmask, const double *coeff, int n_terms,
                     double *out_terms, double *out_sum);
 
+/* qg_expval without any allocation, for callers that cannot allocate memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as qg_expval, with these
+ * differences:
+ *  - n_terms <= 256; more is QG_EINVAL (nothing is launched);
+ *  - masks and coefficients (host arrays, read before the call returns) reach
+ *    the device as kernel arguments; every partial sum lives in one static
+ *    device array of the library, about 2 MiB, held on each device that uses
+ *    it until the process ends; the call allocates no device or pinned host
+ *    memory and clears nothing with hipMemsetAsync;
+ *  - that array is shared by every call on the device and keeps the last
+ *    call's contents: calls that overlap on one device (concurrent streams,
+ *    threads) race and must be ordered by the caller;
+ *  - the state's device must be the current device. */
+qg_status qg_expval_noalloc(qg_state *s, const uint64_t *zmask, const double *coeff, int n_terms,
+                            double *out_terms, double *out_sum);
+
 /* Value and gradient of f = sum_m coeff[m] <Z_{zmask[m]}> for the circuit applied
  * to |0...0>, by one adjoint reverse sweep (Jones & Gacon 2020; the paper's
  * adjoint GPU modes, Sec. 2): for each gate with param_idx >= 0, RX/RY/RZ add

@@ -701,6 +701,8 @@ qg_status qg_state_alloc(int n_qubits, qg_dtype dtype, void *dev_buf, size_t buf
         s->owned = true;
     }
     hipError_t e = launch_zero_state(s->c64(), s->buf, s->dim(), s->cx.stream);
+    // Set-up of this device's allocation-free scratch (address lookup only).
+    if (e == hipSuccess) e = noalloc_scratch_init();
     if (e != hipSuccess) {
         if (s->owned) (void)hipFree(s->buf);
         delete s;
@@ -880,6 +882,20 @@ qg_status qg_expval(qg_state *s, const uint64_t *zmask, const double *coeff, int
                           reinterpret_cast<const double *>(dev + co), n_terms, static_cast<double *>(s->cx.work.p),
                           out_terms, out_sum, s->cx.stream),
             "expval kernels");
+    return QG_OK;
+}
+
+qg_status qg_expval_noalloc(qg_state *s, const uint64_t *zmask, const double *coeff, int n_terms,
+                            double *out_terms, double *out_sum) {
+    if (!s) return fail(QG_EINVAL, "state is NULL");
+    if (n_terms > kNoAllocMaxTerms)
+        return fail(QG_EINVAL, "n_terms = %d exceeds the allocation-free maximum of %d", n_terms, kNoAllocMaxTerms);
+    qg_status st = check_masks(zmask, n_terms, s->n);
+    if (st != QG_OK) return st;
+    if (out_sum && !coeff && n_terms > 0) return fail(QG_EINVAL, "coeff is NULL but out_sum is requested");
+    HIP_TRY(launch_expval_noalloc(s->c64(), s->buf, s->dim(), zmask, coeff, n_terms, out_terms, out_sum,
+                                  s->cx.stream),
+            "expval kernels (allocation-free)");
     return QG_OK;
 }
 

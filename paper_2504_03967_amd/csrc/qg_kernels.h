@@ -25,6 +25,15 @@ hipError_t launch_zero_state(bool c64, void *psi, uint64_t dim, hipStream_t st);
 hipError_t launch_probs(bool c64, const void *psi, uint64_t dim, const uint64_t *idx, int64_t n,
                         double *out, hipStream_t st);
 
+// Allocation-free expectations: masks and coefficients (host arrays) go to the
+// device by value and every partial sum lives in a static device array of the
+// library (kNoAllocMaxTerms terms at most).  noalloc_scratch_init looks up that
+// array's address on the current device.
+constexpr int kNoAllocMaxTerms = 256;
+hipError_t noalloc_scratch_init();
+hipError_t launch_expval_noalloc(bool c64, const void *psi, uint64_t dim, const uint64_t *masks, const double *coeff,
+                                 int n_terms, double *out_terms, double *out_sum, hipStream_t st);
+
 // Z-string expectations.  part: scratch of expval_partials(dim, n_terms) doubles.
 int64_t expval_partials(uint64_t dim, int n_terms);
 hipError_t launch_expval(bool c64, const void *psi, uint64_t dim, const uint64_t *masks,

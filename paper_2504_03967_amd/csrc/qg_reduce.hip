@@ -4,6 +4,8 @@
 // All sums are FP64 (for both amplitude precisions) and use a fixed
 // association order (per-block partials in index order, butterfly wave sums,
 // then a sequential sum over blocks), so repeated calls are bitwise identical.
+#include <mutex>
+
 #include "qg_kernels.h"
 
 namespace qg {
@@ -379,6 +381,90 @@ hipError_t launch_expval(bool c64, const void *psi, uint64_t dim, const uint64_t
     hipLaunchKernelGGL(k_expval_final, dim3(1), dim3(kThreads), 0, st, part, nb, n_terms, coeff, terms, out_terms,
                        out_sum);
     return hipGetLastError();
+}
+
+// ------------------------------------------------ expval without allocation
+
+namespace {
+
+// Scratch of the allocation-free expectation call, one copy per device for the
+// life of the process: masks, coefficients, per-block partials, term sums.
+constexpr int kNoAllocMasksOff = 0;
+constexpr int kNoAllocCoeffOff = kNoAllocMaxTerms;
+constexpr int kNoAllocPartOff = 2 * kNoAllocMaxTerms;
+constexpr int64_t kNoAllocDoubles = 2 * kNoAllocMaxTerms + (int64_t)kNoAllocMaxTerms * 1024 + kNoAllocMaxTerms;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+// Masks and coefficients of up to 64 terms travel by value (no host staging).
+struct TermChunk {
+    uint64_t mask[kTermsPerPass];
+    double coeff[kTermsPerPass];
+};
+
+__global__ void k_stage_terms(const TermChunk c, int count, uint64_t *__restrict__ masks, double *__restrict__ coeff) {
+    const int t = threadIdx.x;
+    if (t < count) {
+        masks[t] = c.mask[t];
+        coeff[t] = c.coeff[t];
+    }
+}
+
+__global__ void k_zero_scalar(double *p) { *p = 0.0; }
+
+// Device address of `scratch` on the current device, looked up once per device.
+hipError_t scratch_address(double **out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double *>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t noalloc_scratch_init() {
+    double *p = nullptr;
+    return scratch_address(&p);
+}
+
+hipError_t launch_expval_noalloc(bool c64, const void *psi, uint64_t dim, const uint64_t *masks,
+                                 const double *coeff, int n_terms, double *out_terms, double *out_sum,
+                                 hipStream_t st) {
+    if (n_terms < 0 || n_terms > kNoAllocMaxTerms) return hipErrorInvalidValue;
+    if (expval_partials(dim, n_terms) > (int64_t)kNoAllocMaxTerms * 1024 + kNoAllocMaxTerms)
+        return hipErrorInvalidValue;
+    if (n_terms == 0) {
+        if (out_sum) hipLaunchKernelGGL(k_zero_scalar, dim3(1), dim3(1), 0, st, out_sum);
+        return hipGetLastError();
+    }
+    double *sc = nullptr;
+    hipError_t e = scratch_address(&sc);
+    if (e != hipSuccess) return e;
+    uint64_t *dm = reinterpret_cast<uint64_t *>(sc + kNoAllocMasksOff);
+    double *dc = sc + kNoAllocCoeffOff;
+    for (int t0 = 0; t0 < n_terms; t0 += kTermsPerPass) {
+        TermChunk c{};
+        const int cnt = n_terms - t0 < kTermsPerPass ? n_terms - t0 : kTermsPerPass;
+        for (int t = 0; t < cnt; ++t) {
+            c.mask[t] = masks[t0 + t];
+            c.coeff[t] = coeff ? coeff[t0 + t] : 0.0;
+        }
+        hipLaunchKernelGGL(k_stage_terms, dim3(1), dim3(kTermsPerPass), 0, st, c, cnt, dm + t0, dc + t0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return launch_expval(c64, psi, dim, dm, dc, n_terms, sc + kNoAllocPartOff, out_terms, out_sum, st);
 }
 
 int64_t sample_tree_doubles(uint64_t dim) {

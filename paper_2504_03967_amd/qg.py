@@ -28,7 +28,7 @@ EXPORTS = (
     "qg_batch_create", "qg_batch_set_params", "qg_batch_launch", "qg_batch_free",
     "qg_mlp_create", "qg_mlp_n_params", "qg_mlp_set_params", "qg_mlp_get_params", "qg_mlp_forward",
     "qg_mlp_grad", "qg_mlp_adam_step", "qg_mlp_train", "qg_mlp_free", "qg_pass_features", "qg_set_cost_model",
-    "qg_autotune",
+    "qg_autotune", "qg_expval_noalloc",
 )
 PASS_FEATURES = 24
 PASS_CONFIGS = 5
@@ -63,6 +63,7 @@ def _load() -> ctypes.CDLL:
         "qg_probs": [P, P, I64, P],
         "qg_sample": [P, I64, U64, P],
         "qg_expval": [P, P, P, ctypes.c_int, P, P],
+        "qg_expval_noalloc": [P, P, P, ctypes.c_int, P, P],
         "qg_adjoint_grad": [P, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, P, P, P],
         "qg_batch_expval": [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P],
         "qg_plan_passes": [P, ctypes.c_int, ctypes.c_int, P, P],
@@ -218,6 +219,19 @@ class State:
                              ctypes.c_void_p(terms.data_ptr()),
                              None if c is None else ctypes.c_void_p(total.data_ptr())))
         return terms, (None if c is None else total[0])
+
+    def expval_noalloc(self, masks: Sequence[int], coeffs: Optional[Sequence[float]],
+                       out_terms: Optional[torch.Tensor], out_sum: Optional[torch.Tensor]) -> None:
+        """qg_expval_noalloc into caller-allocated float64 device tensors (either may be None);
+        the library allocates nothing (at most 256 masks)."""
+        m = np.ascontiguousarray(masks, dtype=np.uint64)
+        c = None if coeffs is None else np.ascontiguousarray(coeffs, dtype=np.float64)
+        for t, k in ((out_terms, m.size), (out_sum, 1)):
+            if t is not None and (t.dtype != torch.float64 or not t.is_contiguous() or t.numel() < k):
+                raise ValueError("outputs must be contiguous float64 tensors of n_terms and 1 elements")
+        _check(lib.qg_expval_noalloc(self.handle, m.ctypes.data, None if c is None else c.ctypes.data, m.size,
+                                     None if out_terms is None else ctypes.c_void_p(out_terms.data_ptr()),
+                                     None if out_sum is None else ctypes.c_void_p(out_sum.data_ptr())))
 
 
 def adjoint_grad(circ, masks, coeffs, n_params: int, dtype="c128", stream=None):
