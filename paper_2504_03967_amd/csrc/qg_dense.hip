@@ -8,8 +8,11 @@
 // wavefront load or store of a row is a contiguous run.  Y = U X is computed in
 // 16x16 output blocks with v_mfma_{f64,f32}_16x16x4: for complex numbers,
 // Yr = Ur Xr + (-Ui) Xi and Yi = Ur Xi + Ui Xr, four real products per k-step.
-// U is read transposed from device memory (UT[c][r] = U[r][c]) so that the 16
-// lanes of an A fragment read consecutive addresses.
+// Each wave owns a 16-row stripe of U (4 waves: 4 stripes at k = 6; at k = 5
+// and 4 the waves of a stripe split its column blocks) and keeps that stripe's
+// A fragments in registers for the whole tile; U is read transposed
+// (UT[c][r] = U[r][c]) so that the 16 lanes of a fragment read consecutive
+// addresses.
 #include "qg_kernels.h"
 
 namespace qg {
@@ -54,12 +57,30 @@ k_dense(const DenseDesc D, const R *__restrict__ ut_re, const R *__restrict__ ut
     using C = typename Mfma<R>::C;
     using Acc = typename Mfma<R>::Acc;
     constexpr int ROWS = 1 << KB;
+    constexpr int NBI = ROWS / 16;       // 16-row stripes of U (and of Y)
+    constexpr int WPI = 4 / NBI;         // waves per stripe
+    constexpr int KS = ROWS / 4;         // k-steps of 4
+    constexpr int kMaxJ = 8;             // column blocks per wave
     const int L = D.l;
     const int COLS = 1 << L;
     extern __shared__ __align__(16) unsigned char smem[];
     C *X = reinterpret_cast<C *>(smem);  // [ROWS][COLS]
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int I = wave % NBI;            // this wave's stripe
+    const int j0 = wave / NBI;           // its column blocks: j0, j0 + WPI, ...
+
+    // The stripe's A fragments for every k-step, read once per tile (U is
+    // shared by all tiles and stays in the caches): A[i][k] = U[16 I + i][s + k]
+    // = UT[s + k][16 I + i], lane (li, lk) holding i = li, k = lk.
+    R ar[KS], ai[KS];
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+        const int ka = 4 * q + lk;
+        ar[q] = ut_re[ka * ROWS + 16 * I + li];
+        ai[q] = ut_im[ka * ROWS + 16 * I + li];
+    }
 
     // Tile base: deposit the block index into the free runs.
     uint64_t gbase = 0;
@@ -83,46 +104,35 @@ k_dense(const DenseDesc D, const R *__restrict__ ut_re, const R *__restrict__ ut
     }
     __syncthreads();
 
-    // Output blocks (I, J) of 16 x 16, dealt to the 4 waves.
-    const int nbi = ROWS / 16, nbj = COLS / 16;
-    const int nblk = nbi * nbj;
-    const int li = lane & 15, lk = lane >> 4;
-    // Each wave accumulates up to kMaxBlk output blocks before anyone overwrites X.
-    constexpr int kMaxBlk = 8;
-    Acc accr[kMaxBlk], acci[kMaxBlk];
+    // Y[16 I .. 16 I + 15][16 J ..] for this wave's column blocks J; for complex
+    // numbers Yr = Ur Xr + (-Ui) Xi and Yi = Ur Xi + Ui Xr.
+    const int nbj = COLS / 16;
+    Acc accr[kMaxJ], acci[kMaxJ];
 #pragma unroll
-    for (int q = 0; q < kMaxBlk; ++q) {
+    for (int q = 0; q < kMaxJ; ++q) {
+        const int J = j0 + WPI * q;
+        if (J < nbj) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            accr[q][r] = (R)0;
-            acci[q][r] = (R)0;
-        }
-    }
+            for (int r = 0; r < 4; ++r) {
+                accr[q][r] = (R)0;
+                acci[q][r] = (R)0;
+            }
 #pragma unroll
-    for (int q = 0; q < kMaxBlk; ++q) {
-        const int blk = wave + 4 * q;
-        if (blk < nblk) {
-            const int I = blk / nbj, J = blk % nbj;
-            for (int s = 0; s < ROWS; s += 4) {
-                // A[i][k] = U[16 I + i][s + k] = UT[s + k][16 I + i]; B[k][j] = X[s + k][16 J + j]
-                const int ka = s + lk;
-                const R ar = ut_re[ka * ROWS + 16 * I + li];
-                const R ai = ut_im[ka * ROWS + 16 * I + li];
-                const C b = X[ka * COLS + 16 * J + li];
-                accr[q] = Mfma<R>::mac(ar, b.x, accr[q]);
-                accr[q] = Mfma<R>::mac(-ai, b.y, accr[q]);
-                acci[q] = Mfma<R>::mac(ar, b.y, acci[q]);
-                acci[q] = Mfma<R>::mac(ai, b.x, acci[q]);
+            for (int t = 0; t < KS; ++t) {
+                const C b = X[(4 * t + lk) * COLS + 16 * J + li];
+                accr[q] = Mfma<R>::mac(ar[t], b.x, accr[q]);
+                accr[q] = Mfma<R>::mac(-ai[t], b.y, accr[q]);
+                acci[q] = Mfma<R>::mac(ar[t], b.y, acci[q]);
+                acci[q] = Mfma<R>::mac(ai[t], b.x, acci[q]);
             }
         }
     }
     __syncthreads();
     // D fragment: lane holds rows 16 I + row(lane / 16, r), column 16 J + lane % 16.
 #pragma unroll
-    for (int q = 0; q < kMaxBlk; ++q) {
-        const int blk = wave + 4 * q;
-        if (blk < nblk) {
-            const int I = blk / nbj, J = blk % nbj;
+    for (int q = 0; q < kMaxJ; ++q) {
+        const int J = j0 + WPI * q;
+        if (J < nbj) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 C y;

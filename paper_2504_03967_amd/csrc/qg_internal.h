@@ -35,7 +35,8 @@ enum OpKind : int32_t {
     OP_DIAG1R = 10, // OP_DIAG1 whose qubit is register slot a
     OP_DIAG2R = 11, // OP_DIAG2 with one qubit on register slot a, the other qubit-ref c
     OP_DIAG2RR = 12,// OP_DIAG2 with both qubits on register slots a and c
-    OP_DIAGRUN = 13 // a run of diagonal ops fused into one factor per amplitude: DiagRun a
+    OP_DIAGRUN = 13,// a run of diagonal ops fused into one factor per amplitude: DiagRun a
+    OP_CXRR = 14    // OP_CX whose control is register slot c: a fixed permutation of the registers
 };
 
 // Qubit reference: r >= 0 is a tile position; r < 0 is global qubit (-1 - r), outside the tile.

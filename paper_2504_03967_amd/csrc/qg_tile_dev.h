@@ -240,18 +240,35 @@ __device__ __forceinline__ void apply_slot_factor(const C (&a)[NS][NR], C (&o)[N
     default: __builtin_unreachable();                                                      \
     }
 
-// Controlled X: exchange the amplitudes of each pair on register slot J
-// where the control bit is 1.  cref >= 0 is the control's tile position;
-// otherwise the control lies outside the tile and fixed_on is its value there.
+// Controlled X whose control is not a register slot (a thread bit, or a qubit
+// outside the tile): one condition per thread, the same for every pair on
+// register slot J.
 template <int J, int NS, int NR, typename C>
-__device__ __forceinline__ void apply_cx(const C (&a)[NS][NR], C (&o)[NS][NR], uint32_t tp, const uint32_t (&ep)[NR],
-                                         int cref, bool fixed_on) {
+__device__ __forceinline__ void apply_cx(const C (&a)[NS][NR], C (&o)[NS][NR], bool on) {
     constexpr int jb = 1 << J;
-    const uint32_t cm = cref >= 0 ? (1u << cref) : 0u;
 #pragma unroll
     for (int e = 0; e < NR; ++e) {
         if (e & jb) continue;
-        const bool on = cm == 0u ? fixed_on : ((tp | ep[e]) & cm) != 0u;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const C x = a[s][e], y = a[s][e | jb];
+            o[s][e] = sel(on, y, x);
+            o[s][e | jb] = sel(on, x, y);
+        }
+    }
+}
+
+// Controlled X with target slot J and control register slot k (uniform): the
+// condition of each pair is a scalar (the element index is a constant after
+// unrolling), so the exchange costs the selects alone.
+template <int J, int NS, int NR, typename C>
+__device__ __forceinline__ void apply_cx_slot(const C (&a)[NS][NR], C (&o)[NS][NR], int k) {
+    constexpr int jb = 1 << J;
+    const uint32_t km = 1u << k;
+#pragma unroll
+    for (int e = 0; e < NR; ++e) {
+        if (e & jb) continue;
+        const bool on = ((uint32_t)e & km) != 0u;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const C x = a[s][e], y = a[s][e | jb];
@@ -450,11 +467,14 @@ __device__ __forceinline__ void apply_op(const DevOp &op, const DiagTables &dt, 
     } else if (kind == OP_MATRX) {
         QG_SLOT_SWITCH(op.a, (apply_matrx<J_>(a, o, m)));
     } else if (kind == OP_CX) {
-        // A control outside the tile is constant over the tile; when it
-        // is 0 every select keeps the input (no branch: a path that leaves the
-        // registers untouched makes the compiler copy all of them).
-        const bool fon = make_bit(op.c, gbase).fixed_one;
-        QG_SLOT_SWITCH(op.a, (apply_cx<J_>(a, o, tp, ep, op.c, fon)));
+        // The control is a thread bit or lies outside the tile (constant over
+        // it); when it is 0 every select keeps the input (no branch: a path
+        // that leaves the registers untouched makes the compiler copy all of
+        // them).
+        const bool on = make_bit(op.c, gbase).of(tp);
+        QG_SLOT_SWITCH(op.a, (apply_cx<J_>(a, o, on)));
+    } else if (kind == OP_CXRR) {
+        QG_SLOT_SWITCH(op.a, (apply_cx_slot<J_>(a, o, op.c)));
     } else if (kind == OP_DIAG1R) {
         QG_SLOT_SWITCH(op.a, (apply_diag1r<J_>(a, o, m)));
     } else if (kind == OP_DIAG2RR) {
