@@ -844,7 +844,12 @@ Program build_program(const std::vector<Gate> &gates, const std::vector<PassRang
                     break;
                 case OP_CX:
                     op.a = slot;
-                    op.c = ref(it.qc);
+                    if (slot_of(it.qc) >= 0) {
+                        op.kind = OP_CXRR;
+                        op.c = slot_of(it.qc);
+                    } else {
+                        op.c = ref(it.qc);
+                    }
                     break;
                 case OP_DIAG1:
                     if (slot_of(it.qa) >= 0) {
