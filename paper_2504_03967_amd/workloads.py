@@ -159,21 +159,32 @@ def uniform_superposition(n: int) -> Circuit:
 
 
 def cx_blocks(n: int, blocks: int, seed: int) -> Circuit:
-    """Random CX-block unitary (the paper's CX-block generator, Alg. 1): each block draws a
-    control q_c, then a target q_t until it differs, and applies RY(q_c), RZ(q_t) with angles
-    uniform in [0, 2 pi), then CX(q_c -> q_t).  Draw order per block: q_c, q_t (redrawn),
-    RY angle, RZ angle."""
+    """Random CX-block unitary (the workload of the paper's Alg. 1, App. D.1): every block is
+    an RY on a control qubit and an RZ on a different target qubit, angles uniform in
+    [0, 2 pi), then CX(control -> target).  The ordered (control, target) pair is uniform over
+    the n (n - 1) pairs of distinct qubits: one draw k below n (n - 1), control k // (n - 1),
+    target the (k mod (n - 1))-th qubit other than the control.  Draw order per block: k, RY
+    angle, RZ angle."""
     rng = SplitMix64(seed)
     b = CircuitBuilder(n)
     for _ in range(blocks):
-        qc = int(rng.below(n)[0])
-        qt = int(rng.below(n)[0])
-        while qt == qc:
-            qt = int(rng.below(n)[0])
+        k = int(rng.below(n * (n - 1))[0])
+        qc, r = divmod(k, n - 1)
+        qt = r if r < qc else r + 1
         b.g1(RY, qc, float(2 * math.pi * rng.uniform(1)[0]))
         b.g1(RZ, qt, float(2 * math.pi * rng.uniform(1)[0]))
         b.g2(CX, qc, qt)
     return b.build()
+
+
+def prune_small_rotations(circ: Circuit, eps: float) -> Circuit:
+    """Approximate form of a circuit (the rotation-angle approximation of App. D.2, whose
+    threshold the paper leaves open): every CP whose angle, taken in (-pi, pi], has magnitude
+    below ``eps`` is dropped; everything else is kept in order.  eps = 0 keeps every gate."""
+    lam = np.remainder(circ.gate_param[:, 0] + math.pi, 2 * math.pi) - math.pi
+    keep = ~((circ.gate_type[:, 0] == CP) & (np.abs(lam) < eps))
+    return Circuit(circ.n_qubits, circ.gate_type[keep].copy(), circ.gate_param[keep].copy(),
+                   circ.param_idx[keep].copy())
 
 
 def random_circuit(n: int, n_gates: int, seed: int, ops: Sequence[int] = tuple(range(10))) -> Circuit:
@@ -245,20 +256,30 @@ def config2(seed: int = SEED_BASE + 1, n_addr: int = 8, n_data: int = 8) -> Tupl
     na = 1 << m
     p = rng.uniform(n_data * na).reshape(n_data, na)
     theta = 2.0 * np.arccos(np.sqrt(p))
-    a_idx = np.arange(na)
-    gj = np.array([gray(j) for j in range(na)])
-    sign = np.array([[(-1.0) ** bin(a & g).count("1") for g in gj] for a in a_idx])  # [a, j]
-    phi = (theta @ sign) / na  # [d, j]
-    b = CircuitBuilder(m + n_data)
-    for q in range(m):
-        b.g1(H, q)
-    for d in range(n_data):
-        for j in range(na):
-            b.g1(RY, m + d, phi[d, j])
-            diff = gray(j) ^ gray((j + 1) % na)
-            ctrl = diff.bit_length() - 1
-            b.g2(CX, ctrl, m + d)
-    return b.build(), p
+    # Walsh transform over the address bits (butterflies), then read at gray(j).
+    wt = theta.copy()
+    h = 1
+    while h < na:
+        v = wt.reshape(n_data, na // (2 * h), 2, h)
+        v[:, :, 0, :], v[:, :, 1, :] = v[:, :, 0, :] + v[:, :, 1, :], v[:, :, 0, :] - v[:, :, 1, :]
+        h *= 2
+    j = np.arange(na)
+    gj = j ^ (j >> 1)
+    phi = wt[:, gj] / na  # [d, j]
+    # control of the CX after step j: the address bit where gray(j) and gray(j + 1 mod 2^m) differ
+    diff = gj ^ np.roll(gj, -1)
+    ctrl = np.floor(np.log2(diff)).astype(np.int32)
+    G = m + 2 * n_data * na
+    gt = np.zeros((G, 3), dtype=np.int32)
+    gp = np.zeros((G, 3), dtype=np.float64)
+    gt[:m, 0], gt[:m, 1], gt[:m, 2] = H, -1, np.arange(m)
+    body_t = gt[m:].reshape(n_data, na, 2, 3)
+    body_p = gp[m:].reshape(n_data, na, 2, 3)
+    tgt = (m + np.arange(n_data))[:, None]
+    body_t[:, :, 0, 0], body_t[:, :, 0, 1], body_t[:, :, 0, 2] = RY, -1, tgt
+    body_p[:, :, 0, 0] = phi
+    body_t[:, :, 1, 0], body_t[:, :, 1, 1], body_t[:, :, 1, 2] = CX, ctrl[None, :], tgt
+    return Circuit(m + n_data, gt, gp, np.full(G, -1, np.int32)), p
 
 
 def config3(n: int, seed: int | None = None, layers: int = 100, with_qft: bool = True) -> Circuit:
@@ -342,14 +363,16 @@ def config5(seed: int = SEED_BASE + 4, n: int = 24, layers: int = 10) -> Circuit
 
 
 SWEEP_PAIRS = ((0, 1), (1, 29), (29, 0), (15, 16), (28, 29))
+SWEEP_DENSE_GATES = 48
 
 
 def sweep(n: int = 30, seed: int = SEED_BASE + 0) -> Tuple[Circuit, Circuit, List[Tuple[str, Circuit]]]:
     """Gate sweep on an n-qubit state: (prep, full, parts).  ``prep`` is one layer of random
     U3 on every qubit; ``parts`` are the timed pieces: U3 on each target t = 0..n-1, then
     CX, CP and SWAP on each pair of ``SWEEP_PAIRS`` (scaled into range for n < 30), then
-    a k-gate group of U3 on k distinct random qubits for k = 2..6.  ``full`` concatenates
-    the parts."""
+    a k-gate group of U3 on k distinct random qubits for k = 2..6, then blocks of
+    SWEEP_DENSE_GATES random gates on 5 and on 6 of the pair qubits (dense-block passes).
+    ``full`` concatenates the parts."""
     rng = SplitMix64(seed)
     pb = CircuitBuilder(n)
     ang = 2 * math.pi * rng.uniform(3 * n)
@@ -375,6 +398,22 @@ def sweep(n: int = 30, seed: int = SEED_BASE + 0) -> Tuple[Circuit, Circuit, Lis
         for q in qs:
             cb.g1(U3, q, *(2 * math.pi * rng.uniform(3)))
         parts.append((f"fused_k{k}", cb.build()))
+    # dense blocks: SWEEP_DENSE_GATES random gates (all ten ops) on 5 and on 6 of the
+    # qubits the pairs above already entangle
+    ent = sorted({q for ab in pairs for q in ab})
+    for k in (5, 6):
+        qs = ent[:k] if k < len(ent) else ent
+        cb = CircuitBuilder(n)
+        for _ in range(SWEEP_DENSE_GATES):
+            op = int(rng.below(10)[0])
+            t = qs[int(rng.below(len(qs))[0])]
+            c = -1
+            if op in TWO_QUBIT:
+                c = qs[int(rng.below(len(qs))[0])]
+                while c == t:
+                    c = qs[int(rng.below(len(qs))[0])]
+            cb.add(op, c, t, 2 * math.pi * rng.uniform(3))
+        parts.append((f"dense_k{k}", cb.build()))
     full = parts[0][1]
     for _, c in parts[1:]:
         full = concat(full, c)

@@ -188,7 +188,7 @@ def test_bench_sweep_at_full_size_sampled_amplitudes(qg, n, dtype, tmp_path, mon
         st = qg.State(n, dtype)
         st.apply(prep, qg.FUSE_NONE)
         for name, circ in parts:
-            st.apply(circ, qg.FUSE_GREEDY if name.startswith("fused") else qg.FUSE_NONE)
+            st.apply(circ, qg.FUSE_GREEDY if name.startswith(("fused", "dense")) else qg.FUSE_NONE)
         amp = factorised_reference(W.concat(prep, full))
         idx = np.concatenate([np.arange(16), W.config3_indices(n, seed=11, count=4080)]).astype(np.int64)
         got = st.tensor[torch.as_tensor(idx, device="cuda")].cpu().numpy().astype(np.complex128)

@@ -65,7 +65,13 @@ def test_sweep_parts():
     assert prep.n_gates == 30
     names = [p[0] for p in parts]
     assert names[:30] == [f"u3_t{t}" for t in range(30)]
-    assert sum(c.n_gates for _, c in parts) == full.n_gates == 30 + 15 + sum(range(2, 7))
+    assert sum(c.n_gates for _, c in parts) == full.n_gates == 30 + 15 + sum(range(2, 7)) + 2 * W.SWEEP_DENSE_GATES
+    # the dense blocks stay on the qubits the CX / CP / SWAP pairs already entangle
+    pair_qubits = {q for a, b in W.SWEEP_PAIRS for q in (a, b)}
+    for name, c in parts[-2:]:
+        assert name.startswith("dense_k")
+        used = set(int(q) for q in c.gate_type[:, 1:].ravel() if q >= 0)
+        assert used <= pair_qubits and len(used) == int(name[-1])
 
 
 def test_cx_blocks_follow_the_generator():
