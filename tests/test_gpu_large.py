@@ -92,7 +92,9 @@ def test_config3_31q_outputs_against_oracle(qg, dtype):
     assert np.max(np.abs(p - pref)) / pref.mean() < (1e-10 if dtype == "c128" else 1e-4)
     terms, _ = st.expval([0, 1 | (1 << (n - 1))])
     t = terms.cpu().numpy()
-    assert abs(t[0] - norm) < (1e-13 if dtype == "c128" else 1e-5)
+    # the norm drifts from 1 by about (gates) x (rounding of the gate matrices): the FP64
+    # oracle's own is 1 - 5.2e-13 here, so it is compared at the amplitude tolerance
+    assert abs(t[0] - norm) < TOL[dtype]
     assert abs(t[1] - zz) < TOL[dtype]
     st.close()
 
