@@ -229,6 +229,25 @@ typedef enum {
 qg_status qg_plan_kernels(const qg_circuit *c, qg_dtype dtype, int fusion_mode,
                           int32_t *kernel_of_pass, int32_t capacity, int32_t *n_passes);
 
+/* HBM bytes a plan moves (host only, no device needed): *n_passes gets its pass
+ * count and *hbm_bytes the bytes its passes read and write in device memory,
+ * each pass counted as one read and one write of every tile it visits (the half
+ * state of a SWAP or CX permutation pass, the tiles a pass conditioned on a
+ * qubit outside its tile skips excluded).  form:
+ *   QG_FORM_APPLY    qg_apply_circuit with fusion_mode;
+ *   QG_FORM_ADJOINT  qg_adjoint_grad: the greedy forward sweep, the observable
+ *                    (read psi twice, write lambda) and the reverse sweep over
+ *                    both states (fusion_mode ignored);
+ *   QG_FORM_BATCHED  one circuit of qg_batch_expval (fusion_mode ignored): 0 for
+ *                    a circuit whose state fits one tile (registers and LDS
+ *                    only), else its scratch state initialised, streamed once
+ *                    per pass and read by the observable (n_qubits <= 22).
+ * Either output may be NULL.  Errors: QG_EINVAL for an invalid circuit, dtype,
+ * form or fusion mode. */
+typedef enum { QG_FORM_APPLY = 0, QG_FORM_ADJOINT = 1, QG_FORM_BATCHED = 2 } qg_form;
+qg_status qg_plan_bytes(const qg_circuit *c, qg_dtype dtype, int form, int fusion_mode, int32_t *n_passes,
+                        double *hbm_bytes);
+
 /* ---- Learned fusion: the cost model (not in the paper; its backend fixes the
  * fusion width at 5, App. D.2).  An MLP with three ReLU hidden layers of width
  * 64 and a linear scalar output, FP32, run by the library's own forward,
@@ -278,8 +297,12 @@ qg_status qg_set_cost_model(qg_mlp *m);
 
 /* Process-wide planner tuning (not part of the paper's method; performance only,
  * results are identical up to rounding for every setting).  Keys:
- *   dense_min_gates                  a greedy pass touching <= 6 qubits with at least
- *                                    this many gates runs as a dense MFMA block
+ *   dense_min_gates                  a run of gates touching <= 6 qubits with at least
+ *                                    this many gates runs as one dense MFMA block;
+ *                                    0 (default): the break-even measured on MI355X
+ *                                    per precision and block width (36 / 36 / 32 gates
+ *                                    for 4 / 5 / 6 qubits in complex128, 20 / 20 / 24
+ *                                    in complex64); 1 << 30: never
  *   tile_bits_c128 / tile_bits_c64   qubits per tile (amplitudes streamed per workgroup)
  *   reg_bits_c128 / reg_bits_c64     amplitudes per thread = 2^reg_bits
  *   low_bits_c128 / low_bits_c64     lowest qubits kept in every fused tile

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <cstdarg>
@@ -309,6 +310,7 @@ PlanConfig batch_config(int n, bool c64) {
     cfg.max_gates_per_pass = n <= cfg.tile_bits ? (1 << 30) : 4096;
     cfg.use_classes = false;  // the persistent kernel is built for one register width
     cfg.diag_run_min = 0;     // its programs carry no fused diagonal runs
+    cfg.dense_min_gates = 1 << 30;  // nor dense blocks
     cfg.half_lds = false;     // its LDS is sized for whole complex values; registers limit occupancy
     clamp_config(&cfg);
     return cfg;
@@ -525,6 +527,10 @@ hipError_t mlp_act(qg_mlp *M, int B, int loss_slots, MlpAct *a) {
 }
 
 qg_mlp *g_cost_model = nullptr;
+// Bumped whenever an input of learned planning changes (the installed model or
+// its parameters, tuning keys, autotuned shapes): cached learned plans older
+// than the current value are dropped.
+std::atomic<uint64_t> g_planning_gen{1};
 static_assert(kPlanFeatures == QG_PASS_FEATURES && kPlanConfigs == QG_PASS_CONFIGS && kPlanDense == QG_PASS_DENSE,
               "feature layout");
 
@@ -542,7 +548,8 @@ struct PlanEntry {
 
 std::mutex g_plan_mu;
 std::map<uint64_t, PlanEntry> g_plan_cache;
-const qg_mlp *g_plan_cache_model = nullptr;
+uint64_t g_plan_cache_gen = 0;
+constexpr size_t kPlanCacheMax = 256;
 
 uint64_t structure_hash(int n, bool c64, const std::vector<Gate> &g) {
     uint64_t h = 1469598103934665603ull;
@@ -574,9 +581,9 @@ qg_status learned_plan(const std::vector<Gate> &g0, int n, bool c64, PlanEntry *
     const std::vector<Gate> g = permute(g0, sc.order);
     {
         std::lock_guard<std::mutex> lk(g_plan_mu);
-        if (g_plan_cache_model != g_cost_model) {
+        if (g_plan_cache_gen != g_planning_gen.load()) {
             g_plan_cache.clear();
-            g_plan_cache_model = g_cost_model;
+            g_plan_cache_gen = g_planning_gen.load();
         }
         auto it = g_plan_cache.find(structure_hash(n, c64, g0));
         if (it != g_plan_cache.end()) {
@@ -634,6 +641,7 @@ qg_status learned_plan(const std::vector<Gate> &g0, int n, bool c64, PlanEntry *
         i = c.j;
     }
     std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (g_plan_cache.size() >= kPlanCacheMax) g_plan_cache.clear();
     g_plan_cache[structure_hash(n, c64, g0)] = *out;
     return QG_OK;
 }
@@ -666,6 +674,7 @@ const char *qg_version(void) { return "qgear-mi355x 0.1 (gfx950)"; }
 qg_status qg_set_tuning(const char *key, int64_t value) {
     if (!key) return fail(QG_EINVAL, "key is NULL");
     if (set_tuning(key, value) != 0) return fail(QG_EINVAL, "unknown tuning key or value out of range: %s = %lld", key, (long long)value);
+    ++g_planning_gen;
     return QG_OK;
 }
 
@@ -801,6 +810,84 @@ qg_status qg_plan_kernels(const qg_circuit *c, qg_dtype dtype, int fusion_mode, 
                                                : QG_KERNEL_TILE;
     }
     if (n_passes) *n_passes = np;
+    return QG_OK;
+}
+
+namespace {
+
+// HBM bytes one pass moves for one state: every active tile (or dense-block
+// tile) read and written once; the permutation and lane kernels move the half or
+// whole state they visit.
+double pass_hbm_bytes(const Program &prog, const PassDesc &pd, int n, bool c64) {
+    const double S = c64 ? 8.0 : 16.0;
+    const int line_bits = c64 ? 4 : 3;
+    if (pd.flags & PASS_SWAP2) return 2.0 * std::ldexp(1.0, n - 1) * S;
+    if (pd.flags & PASS_SWAPL) return 2.0 * std::ldexp(1.0, n) * S;
+    if (pd.flags & PASS_LANE1) return 2.0 * std::ldexp(1.0, pd.run_start[1] >= line_bits ? n - 1 : n) * S;
+    if (pd.flags & PASS_DENSE) {
+        const DenseDesc &D = prog.dense[pd.phase_begin];
+        return 2.0 * (double)D.n_tiles * std::ldexp(1.0, D.k + D.l) * S;
+    }
+    return 2.0 * (double)pd.n_tiles * std::ldexp(1.0, pd.b) * S;
+}
+
+double program_hbm_bytes(const Program &prog, int n, bool c64, int states) {
+    double b = 0.0;
+    for (const PassDesc &pd : prog.passes) b += states * pass_hbm_bytes(prog, pd, n, c64);
+    return b;
+}
+
+}  // namespace
+
+qg_status qg_plan_bytes(const qg_circuit *c, qg_dtype dtype, int form, int fusion_mode, int32_t *n_passes,
+                        double *hbm_bytes) {
+    std::string err;
+    if (validate_circuit(c, -1, &err) != QG_OK)
+        return fail(QG_EINVAL, "%s", err.c_str());
+    if (dtype != QG_C64 && dtype != QG_C128) return fail(QG_EINVAL, "unknown dtype %d", (int)dtype);
+    if (form < QG_FORM_APPLY || form > QG_FORM_BATCHED) return fail(QG_EINVAL, "unknown form %d", form);
+    if (form == QG_FORM_APPLY && (fusion_mode < QG_FUSE_NONE || fusion_mode > QG_FUSE_LEARNED))
+        return fail(QG_EINVAL, "unknown fusion mode %d", fusion_mode);
+    const bool c64 = dtype == QG_C64;
+    const int n = c->n_qubits;
+    const double S = c64 ? 8.0 : 16.0, state = std::ldexp(1.0, n) * S;
+    std::vector<Gate> g = load_gates(c);
+    int32_t np = 0;
+    double bytes = 0.0;
+    if (form == QG_FORM_APPLY) {
+        Program prog;
+        if (fusion_mode == QG_FUSE_LEARNED) {
+            PlanEntry e;
+            qg_status st = learned_plan(g, n, c64, &e);
+            if (st != QG_OK) return st;
+            prog = build_learned(g, e, n, c64);
+        } else {
+            prog = build_plan(g, plan_config(n, c64, fusion_mode));
+        }
+        np = (int32_t)prog.passes.size();
+        bytes = program_hbm_bytes(prog, n, c64, 1);
+    } else if (form == QG_FORM_ADJOINT) {
+        // forward sweep (greedy), <O> and lambda = O psi (read psi twice, write
+        // lambda), then the reverse sweep over both states
+        PlanConfig fcfg = plan_config(n, c64, QG_FUSE_GREEDY);
+        Program fwd = build_plan(g, fcfg);
+        PlanConfig rcfg = fcfg;
+        rcfg.reverse = true;
+        clamp_config(&rcfg);
+        Program rev = build_plan(execution_order(g, true), rcfg);
+        np = (int32_t)(fwd.passes.size() + rev.passes.size());
+        bytes = state + program_hbm_bytes(fwd, n, c64, 1) + 3.0 * state + program_hbm_bytes(rev, n, c64, 2);
+    } else {
+        if (n > kBatchMaxQubits) return fail(QG_EINVAL, "n_qubits = %d above the batched form's %d", n, kBatchMaxQubits);
+        Program prog = build_plan(g, batch_config(n, c64));
+        np = (int32_t)prog.passes.size();
+        // a state of one tile stays in registers and LDS; a larger one lives in
+        // HBM scratch: initialised, streamed once per pass, read by the observable
+        const bool one_tile = prog.passes.size() == 1 && prog.passes[0].n_tiles == 1;
+        bytes = one_tile ? 0.0 : 2.0 * state + program_hbm_bytes(prog, n, c64, 1);
+    }
+    if (n_passes) *n_passes = np;
+    if (hbm_bytes) *hbm_bytes = bytes;
     return QG_OK;
 }
 
@@ -1164,6 +1251,7 @@ qg_status qg_mlp_set_params(qg_mlp *M, const float *theta) {
     HIP_TRY(hipMemsetAsync(M->m.p, 0, M->P * sizeof(float), M->stream), "reset adam");
     HIP_TRY(hipMemsetAsync(M->v.p, 0, M->P * sizeof(float), M->stream), "reset adam");
     HIP_TRY(hipStreamSynchronize(M->stream), "set params");
+    if (M == g_cost_model) ++g_planning_gen;
     M->step = 0;
     return QG_OK;
 }
@@ -1215,6 +1303,7 @@ qg_status qg_mlp_grad(qg_mlp *M, const float *x, const float *t, int B, double *
 
 qg_status qg_mlp_adam_step(qg_mlp *M, const float *grad, float lr) {
     if (!M || !grad) return fail(QG_EINVAL, "NULL argument");
+    if (M == g_cost_model) ++g_planning_gen;
     HIP_TRY(hipMemcpyAsync(M->grad.p, grad, M->P * sizeof(float), hipMemcpyHostToDevice, M->stream), "adam grad");
     M->step++;
     HIP_TRY(launch_mlp_adam(static_cast<float *>(M->theta.p), static_cast<float *>(M->grad.p),
@@ -1228,6 +1317,7 @@ qg_status qg_mlp_train(qg_mlp *M, const float *x, const float *t, int N, int epo
                        uint64_t seed, double *loss_per_epoch) {
     if (!M || !x || !t) return fail(QG_EINVAL, "NULL argument");
     if (N < 1 || epochs < 0 || batch < 1) return fail(QG_EINVAL, "N, epochs or batch out of range");
+    if (M == g_cost_model) ++g_planning_gen;
     if (batch > N) batch = N;
     const size_t F = M->F;
     const size_t xb = ((size_t)N * F * sizeof(float) + 255) & ~size_t(255);
@@ -1289,7 +1379,10 @@ qg_status qg_mlp_train(qg_mlp *M, const float *x, const float *t, int N, int epo
 
 qg_status qg_mlp_free(qg_mlp *M) {
     if (!M) return QG_OK;
-    if (g_cost_model == M) g_cost_model = nullptr;
+    if (g_cost_model == M) {
+        g_cost_model = nullptr;
+        ++g_planning_gen;
+    }
     (void)hipStreamSynchronize(M->stream);
     delete M;
     return QG_OK;
@@ -1320,6 +1413,7 @@ qg_status qg_set_cost_model(qg_mlp *M) {
     if (M && M->F != kPlanFeatures)
         return fail(QG_EINVAL, "cost model takes %d inputs, pass features are %d", M->F, kPlanFeatures);
     g_cost_model = M;
+    ++g_planning_gen;
     return QG_OK;
 }
 
@@ -1450,6 +1544,7 @@ qg_status qg_autotune(qg_state *s, int reps, int32_t *table) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    ++g_planning_gen;
     if (result != QG_OK) return result;
     HIP_TRY(launch_zero_state(c64, s->buf, s->dim(), s->cx.stream), "state init");
     if (table)

@@ -10,6 +10,8 @@
 #include "qg_plan.h"
 
 #include <algorithm>
+#include <queue>
+#include <set>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -152,7 +154,7 @@ const Knob kKnobs[] = {
     {"half_lds_c128", [](Tuning &t) { return &t.half_lds[0]; }, 0, 1},
     {"half_lds_c64", [](Tuning &t) { return &t.half_lds[1]; }, 0, 1},
     {"pipe_min_ops", [](Tuning &t) { return &t.pipe_min_ops; }, 1, 1 << 20},
-    {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 1, 1 << 30},
+    {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 0, 1 << 30},
 };
 
 // A phase of a pass: the tile positions held in registers (slot order) and
@@ -226,49 +228,94 @@ bool items_commute(const Item &x, const Item &y) {
 
 // Fewer register layouts (each change is an LDS exchange of the whole tile):
 // items may run in any order that keeps every non-commuting pair in its given
-// order.  A phase runs every ready item it can; when none is left it takes the
-// register qubit of the earliest ready item (for the first phase, one at or
-// above the cache-line bits if any, so that the loads stay line-aligned),
-// until rb qubits are held.
+// order.  A phase runs every ready item it can (smallest index first); when
+// none is left it takes the register qubit of the earliest ready item (for the
+// first phase, one at or above the cache-line bits if any, so that the loads
+// stay line-aligned), until rb qubits are held.
+//
+// The order constraints are kept as a graph whose transitive closure is the
+// non-commuting pairs: per qubit, an item that is diagonal on it follows the
+// last item that is not; an item that is not diagonal on it follows that item
+// and every diagonal item since.  So planning a pass of thousands of gates
+// (QCrank's) costs time linear in its items, not quadratic.
 std::vector<PhasePlan> plan_phases(const std::vector<Item> &items, const int *pos_of, int b, int rb, int line_bits) {
     const int n = (int)items.size();
-    std::vector<std::vector<int>> pred(n);
-    for (int j = 0; j < n; ++j)
-        for (int i = 0; i < j; ++i)
-            if (!items_commute(items[i], items[j])) pred[j].push_back(i);
-    std::vector<char> done(n, 0);
-    int left = n;
-    auto ready = [&](int j) {
-        if (done[j]) return false;
-        for (int i : pred[j])
-            if (!done[i]) return false;
-        return true;
-    };
-    std::vector<PhasePlan> out;
-    do {
-        PhasePlan pp;
-        for (;;) {
-            bool progress = true;
-            while (progress) {
-                progress = false;
-                for (int j = 0; j < n; ++j) {
-                    if (!ready(j)) continue;
-                    const int q = needs_register(items[j]);
-                    if (q >= 0 && std::find(pp.S.begin(), pp.S.end(), pos_of[q]) == pp.S.end()) continue;
-                    done[j] = 1;
-                    --left;
-                    pp.items.push_back(j);
-                    progress = true;
+    std::vector<std::vector<int>> succ(n);
+    std::vector<int> indeg(n, 0);
+    {
+        std::vector<int> last_nd(64, -1);
+        std::vector<std::vector<int>> diag_since(64);
+        for (int j = 0; j < n; ++j) {
+            int qs[2];
+            bool dg[2];
+            const int nq = item_qubits(items[j], qs, dg);
+            for (int k = 0; k < nq; ++k) {
+                const int q = qs[k];
+                auto edge = [&](int i) {
+                    if (i >= 0 && i != j) {
+                        succ[i].push_back(j);
+                        ++indeg[j];
+                    }
+                };
+                edge(last_nd[q]);
+                if (dg[k]) {
+                    diag_since[q].push_back(j);
+                } else {
+                    for (int i : diag_since[q]) edge(i);
+                    diag_since[q].clear();
+                    last_nd[q] = j;
                 }
             }
-            if (left == 0 || (int)pp.S.size() >= rb) break;
+        }
+    }
+    // Ready items that need a register qubit outside the current layout wait
+    // in `waiting` (ordered by index) and in the bucket of their tile position.
+    std::set<int> waiting;
+    std::vector<std::vector<int>> bucket(64);
+    std::priority_queue<int, std::vector<int>, std::greater<int>> runnable;
+    std::vector<PhasePlan> out;
+    PhasePlan pp;
+    auto in_S = [&](int p) { return std::find(pp.S.begin(), pp.S.end(), p) != pp.S.end(); };
+    auto make_ready = [&](int j) {
+        const int q = needs_register(items[j]);
+        if (q < 0 || in_S(pos_of[q])) {
+            runnable.push(j);
+        } else {
+            waiting.insert(j);
+            bucket[pos_of[q]].push_back(j);
+        }
+    };
+    for (int j = 0; j < n; ++j)
+        if (indeg[j] == 0) make_ready(j);
+    int left = n;
+    do {
+        pp = PhasePlan();
+        for (;;) {
+            while (!runnable.empty()) {
+                const int j = runnable.top();
+                runnable.pop();
+                pp.items.push_back(j);
+                --left;
+                for (int k : succ[j])
+                    if (--indeg[k] == 0) make_ready(k);
+            }
+            if (left == 0 || (int)pp.S.size() >= rb || waiting.empty()) break;
             int pick = -1;
-            for (int j = 0; j < n && pick < 0; ++j)
-                if (ready(j) && (!out.empty() || pos_of[needs_register(items[j])] >= line_bits)) pick = j;
-            for (int j = 0; j < n && pick < 0; ++j)
-                if (ready(j)) pick = j;
-            if (pick < 0) break;
-            pp.S.push_back(pos_of[needs_register(items[pick])]);
+            if (out.empty()) {
+                for (int j : waiting)
+                    if (pos_of[needs_register(items[j])] >= line_bits) {
+                        pick = j;
+                        break;
+                    }
+            }
+            if (pick < 0) pick = *waiting.begin();
+            const int p = pos_of[needs_register(items[pick])];
+            pp.S.push_back(p);
+            for (int j : bucket[p]) {
+                waiting.erase(j);
+                runnable.push(j);
+            }
+            bucket[p].clear();
         }
         fill_slots(&pp.S, b, rb);
         out.push_back(pp);
@@ -537,16 +584,25 @@ std::vector<PassRange> fuse(const std::vector<Gate> &g, const PlanConfig &cfg) {
 // Runs of consecutive gates (in the given order) that touch at most 6 qubits and
 // hold at least dense_min_gates gates: each becomes a pass of its own, which the
 // plan then executes as one dense block.  Greedy from the left, longest run
-// from each start.  Empty when dense blocks are off.
+// from each start.  Empty when dense blocks are off or on the automatic
+// threshold.
 std::vector<PassRange> dense_runs(const std::vector<Gate> &g, const PlanConfig &cfg) {
     std::vector<PassRange> runs;
     const int G = (int)g.size();
-    if (cfg.reverse || cfg.n < 8 || cfg.dense_min_gates >= (1 << 30) || cfg.fusion == QG_FUSE_NONE) return runs;
+    // Only an explicit threshold cuts runs out of the schedule.  Under the measured
+    // break-even (dense_min_gates = 0) a greedy pass that happens to touch <= 6
+    // qubits becomes a dense block instead, because a run cut out of a larger
+    // pass adds a pass of its own (QCrank's Gray-code runs, for one, fit 6 qubits
+    // for 62 gates inside passes of thousands).
+    if (cfg.reverse || cfg.n < 8 || cfg.dense_min_gates <= 0 || cfg.dense_min_gates >= (1 << 30) ||
+        cfg.fusion == QG_FUSE_NONE)
+        return runs;
     for (int i = 0; i < G;) {
         uint64_t q = 0;
         int j = i;
         while (j < G && popcount64(q | touched_qubits(g[j])) <= 6) q |= touched_qubits(g[j++]);
-        if (j - i >= cfg.dense_min_gates && dense_block_qubits(g, i, j, cfg.n)) {
+        const uint64_t blk = j > i ? dense_block_qubits(g, i, j, cfg.n) : 0;
+        if (blk && j - i >= dense_threshold(cfg, popcount64(blk))) {
             runs.push_back({i, j});
             i = j;
         } else {
@@ -554,6 +610,12 @@ std::vector<PassRange> dense_runs(const std::vector<Gate> &g, const PlanConfig &
         }
     }
     return runs;
+}
+
+int dense_threshold(const PlanConfig &cfg, int k) {
+    if (cfg.dense_min_gates > 0) return cfg.dense_min_gates;
+    const int kk = k < 4 ? 4 : k > 6 ? 6 : k;
+    return tuning().dense_auto[cfg.c64 ? 1 : 0][kk - 4];
 }
 
 Schedule schedule(const std::vector<Gate> &g, const PlanConfig &cfg) {
@@ -1086,8 +1148,9 @@ Program build_plan(const std::vector<Gate> &g0, const PlanConfig &cfg, std::vect
             prog.pass_of_gate[r.g_begin] = (int)p;
             continue;
         }
-        const uint64_t blk = (!cfg.reverse && cfg.n >= 8 && r.g_end - r.g_begin >= cfg.dense_min_gates)
-                                 ? dense_block_qubits(g, r.g_begin, r.g_end, cfg.n) : 0;
+        uint64_t blk = (!cfg.reverse && cfg.n >= 8 && cfg.dense_min_gates < (1 << 30))
+                           ? dense_block_qubits(g, r.g_begin, r.g_end, cfg.n) : 0;
+        if (blk && r.g_end - r.g_begin < dense_threshold(cfg, popcount64(blk))) blk = 0;
         if (blk) {
             append_dense(&prog, g, r.g_begin, r.g_end, blk, cfg);
         } else {

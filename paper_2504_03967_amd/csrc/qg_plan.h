@@ -31,7 +31,8 @@ struct PlanConfig {
     int nt_mode = 1;      // 0 off, 1 only for line-aligned layouts, 2 always
     int swz_bits = 0;     // tile-order swizzle of the block index
     int max_gates_per_pass = 4096;
-    int dense_min_gates = 1 << 30;  // a pass on <= 6 qubits with this many gates runs as a dense block
+    int dense_min_gates = 0;  // a run on <= 6 qubits with this many gates runs as a dense block;
+                              // 0: the measured break-even of Tuning::dense_auto; 1 << 30: never
     bool use_classes = true;        // single-gate passes take their tile shape from the class table
     int diag_run_min = 3;           // consecutive diagonal ops fused into one (0: never)
     bool half_lds = false;          // multi-phase passes exchange real and imaginary parts in turn
@@ -65,7 +66,11 @@ struct Tuning {
     int half_lds[2] = {1, 0};
     int pipe = 0;          // persistent prefetching blocks: 0 never, 1 heavy passes, 2 always
     int pipe_min_ops = 4;  // a pass is heavy with several phases or at least this many ops
-    int dense_min_gates = 1 << 30;
+    int dense_min_gates = 0;
+    // Gates from which a run on k = 4, 5, 6 qubits runs faster as one dense block
+    // than as a tile pass, [c128, c64][k - 4] (measured on MI355X at 30 qubits
+    // complex128 and 31 complex64, random gates of all ten kinds).
+    int dense_auto[2][3] = {{36, 36, 32}, {20, 20, 24}};
     // Per pass class (see pass_class): tile bits, register bits and swizzle of
     // single-gate passes, and the swizzle of fused passes.  [dtype][class]
     int cls_tile[2][kPassClasses] = {{12, 12, 12, 10, 12}, {13, 13, 13, 11, 13}};
@@ -137,6 +142,9 @@ uint64_t touched_qubits(const Gate &g);
 void append_dense(Program *prog, const std::vector<Gate> &g, int begin, int end, uint64_t blk, const PlanConfig &cfg);
 // Block qubits for a dense step of gates [begin, end), or 0 if they touch more than 6 qubits.
 uint64_t dense_block_qubits(const std::vector<Gate> &g, int begin, int end, int n);
+// Gates a run on `k` block qubits (4..6, after padding) needs to run as a dense block.
+int dense_threshold(const PlanConfig &cfg, int k);
+
 // Greedy plan (commutation-aware schedule) with the dense rule applied (cfg.dense_min_gates).
 // *order (may be NULL) receives the execution order of the gates.
 Program build_plan(const std::vector<Gate> &g, const PlanConfig &cfg, std::vector<int> *order = nullptr);

@@ -28,7 +28,7 @@ EXPORTS = (
     "qg_batch_create", "qg_batch_set_params", "qg_batch_launch", "qg_batch_free",
     "qg_mlp_create", "qg_mlp_n_params", "qg_mlp_set_params", "qg_mlp_get_params", "qg_mlp_forward",
     "qg_mlp_grad", "qg_mlp_adam_step", "qg_mlp_train", "qg_mlp_free", "qg_pass_features", "qg_set_cost_model",
-    "qg_autotune", "qg_expval_noalloc",
+    "qg_autotune", "qg_expval_noalloc", "qg_plan_bytes",
 )
 PASS_FEATURES = 24
 PASS_CONFIGS = 5
@@ -68,6 +68,7 @@ def _load() -> ctypes.CDLL:
         "qg_batch_expval": [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P],
         "qg_plan_passes": [P, ctypes.c_int, ctypes.c_int, P, P],
         "qg_plan_kernels": [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int32, P],
+        "qg_plan_bytes": [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P],
         "qg_batch_create": [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P],
         "qg_batch_set_params": [P, P],
         "qg_batch_launch": [P],
@@ -407,6 +408,20 @@ def plan_passes(circ, dtype="c128", fusion: int = FUSE_GREEDY):
     npass = ctypes.c_int32()
     _check(lib.qg_plan_passes(ca.ptr, _dtype_code(dtype), int(fusion), pog.ctypes.data, ctypes.byref(npass)))
     return pog[:ca.gt.shape[0]], int(npass.value)
+
+
+FORM_APPLY, FORM_ADJOINT, FORM_BATCHED = 0, 1, 2
+
+
+def plan_bytes(circ, dtype="c128", form: int = FORM_APPLY, fusion: int = FUSE_GREEDY):
+    """(passes, HBM bytes the plan moves) of qg_apply_circuit (form FORM_APPLY, with
+    `fusion`), qg_adjoint_grad (FORM_ADJOINT) or one batched circuit (FORM_BATCHED)."""
+    ca = CircuitArgs(circ)
+    npass = ctypes.c_int32()
+    b = ctypes.c_double()
+    _check(lib.qg_plan_bytes(ca.ptr, _dtype_code(dtype), int(form), int(fusion), ctypes.byref(npass),
+                             ctypes.byref(b)))
+    return int(npass.value), float(b.value)
 
 
 KERNEL_NAMES = ("tile", "dense", "swap_half", "swap_lane", "lane_gate")
