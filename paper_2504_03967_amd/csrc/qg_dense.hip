@@ -92,15 +92,29 @@ k_dense(const DenseDesc D, const R *__restrict__ ut_re, const R *__restrict__ ut
             w >>= len;
         }
     }
-    // Load: thread covers column c = tid % COLS of rows tid / COLS, + 256 / COLS, ...
-    const int cstep = 256 < COLS ? 256 : COLS;
-    const int rstep = 256 / cstep;
+    // Global offsets of the block-qubit patterns (rows), once per tile, in LDS
+    // after the tile.  A thread covers columns c0, c0 + cstep, ... and in each
+    // the rows r0, r0 + rstep, ...; loads go out in groups of 8 before their
+    // stores to LDS, so that each thread keeps several in flight.
+    uint64_t *rowoff = reinterpret_cast<uint64_t *>(X + (ROWS << L));
+    if (tid < ROWS) rowoff[tid] = deposit(tid, D.blk_q, KB);
+    const int cstep = COLS < 256 ? COLS : 256;
+    const int rstep = 256 / cstep;  // <= 16 <= ROWS
     const int c0 = tid % cstep;
     const int r0 = tid / cstep;
+    const int nrow = ROWS / rstep;
+    __syncthreads();
     for (int c = c0; c < COLS; c += cstep) {
-        const uint64_t cg = deposit(c, D.low_q, L);
-        for (int r = r0; r < ROWS; r += rstep)
-            X[r * COLS + c] = psi[gbase | cg | deposit(r, D.blk_q, KB)];
+        const uint64_t cg = gbase | deposit(c, D.low_q, L);
+        int q0 = 0;
+        for (; q0 + 8 <= nrow; q0 += 8) {
+            C v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = psi[cg | rowoff[r0 + (q0 + q) * rstep]];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) X[(r0 + (q0 + q) * rstep) * COLS + c] = v[q];
+        }
+        for (; q0 < nrow; ++q0) X[(r0 + q0 * rstep) * COLS + c] = psi[cg | rowoff[r0 + q0 * rstep]];
     }
     __syncthreads();
 
@@ -144,16 +158,16 @@ k_dense(const DenseDesc D, const R *__restrict__ ut_re, const R *__restrict__ ut
     }
     __syncthreads();
     for (int c = c0; c < COLS; c += cstep) {
-        const uint64_t cg = deposit(c, D.low_q, L);
-        for (int r = r0; r < ROWS; r += rstep)
-            psi[gbase | cg | deposit(r, D.blk_q, KB)] = X[r * COLS + c];
+        const uint64_t cg = gbase | deposit(c, D.low_q, L);
+        for (int q0 = 0; q0 < nrow; ++q0) psi[cg | rowoff[r0 + q0 * rstep]] = X[(r0 + q0 * rstep) * COLS + c];
     }
 }
 
 template <typename R, int KB>
 hipError_t launch_k(const DenseDesc &D, const void *ut_re, const void *ut_im, void *psi, hipStream_t st) {
     using C = typename Mfma<R>::C;
-    const size_t lds = (size_t(1) << (KB + D.l)) * sizeof(C);
+    // the tile, then the 2^k row offsets (uint64)
+    const size_t lds = (size_t(1) << (KB + D.l)) * sizeof(C) + (size_t(8) << KB);
     if (lds > 65536) {
         static bool done = false;
         if (!done) {

@@ -671,13 +671,24 @@ __device__ __forceinline__ void tile_phases(const PassDesc &P, const PhaseDesc *
         // Each op reads one register set and writes the other, so that no op
         // has to update its inputs in place (which costs a copy of every
         // register per op at the loop's back edge).
+        // The descriptor of the op after next is loaded while the current pair
+        // runs: a long program does not fit the scalar cache, and a descriptor
+        // fetched only when its op starts would expose the memory latency once
+        // per op.  (The look-ahead index stays inside the phase.)
         C b[NS][NR];
+        const int end = ph.op_end;
         int i = ph.op_begin;
-        for (; i + 1 < ph.op_end; i += 2) {
-            apply_op<R, RB, NS>(ops[i], dt, a, b, gbase, tp, ep, gpart, gstride, tile_idx, tid);
-            apply_op<R, RB, NS>(ops[i + 1], dt, b, a, gbase, tp, ep, gpart, gstride, tile_idx, tid);
+        if (i < end) {
+            DevOp c0 = ops[i];
+            for (; i + 1 < end; i += 2) {
+                const DevOp c1 = ops[i + 1];
+                apply_op<R, RB, NS>(c0, dt, a, b, gbase, tp, ep, gpart, gstride, tile_idx, tid);
+                const DevOp c2 = ops[i + 2 < end ? i + 2 : end - 1];
+                apply_op<R, RB, NS>(c1, dt, b, a, gbase, tp, ep, gpart, gstride, tile_idx, tid);
+                c0 = c2;
+            }
+            if (i < end) apply_op<R, RB, NS>(c0, dt, a, a, gbase, tp, ep, gpart, gstride, tile_idx, tid);
         }
-        if (i < ph.op_end) apply_op<R, RB, NS>(ops[i], dt, a, a, gbase, tp, ep, gpart, gstride, tile_idx, tid);
     }
 }
 
