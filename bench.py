@@ -62,6 +62,11 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="omit the adjoint / batched speed-ups and the learned-fusion gain")
     ap.add_argument("--cm-samples", type=int, default=1500, help="timed passes for the cost-model dataset")
+    ap.add_argument("--form-only", choices=["adjoint", "batched"], default="",
+                    help="only run the adjoint gradient (24 qubits) or the batched launch (4096 circuits) "
+                         "twice, for profiling")
+    ap.add_argument("--paper-workloads", action="store_true",
+                    help="only run the paper's short and long CX-block unitaries at 28-34 qubits (minutes)")
     ap.add_argument("--config3-only", type=int, default=0, metavar="N",
                     help="only time config 3 on N qubits (c128) and print its JSON line (profiling)")
     return ap.parse_args()
@@ -121,12 +126,10 @@ def config3_timing(qg, W, torch, n: int = 31):
 
 
 def paper_shaped(qg, W, torch, n: int = 30):
-    """The paper's other benchmark circuit shapes at n qubits (complex128, greedy fusion):
-    QFT(n), and random CX-block unitaries of 100 ('short') and 1000 blocks."""
+    """The QFT at n qubits (complex128, greedy fusion)."""
     st = qg.State(n, "c128")
     out = {}
-    for name, circ in (("qft", W.qft(n).build()), ("cx_blocks_100", W.cx_blocks(n, 100, W.SEED_BASE + 7)),
-                       ("cx_blocks_1000", W.cx_blocks(n, 1000, W.SEED_BASE + 8))):
+    for name, circ in (("qft", W.qft(n).build()),):
         _, npass = qg.plan_passes(circ, "c128", qg.FUSE_GREEDY)
         st.apply(circ, qg.FUSE_GREEDY)  # warm-up
         torch.cuda.synchronize()
@@ -187,6 +190,148 @@ def precision_gap(qg, W, torch, n: int = 26):
             "fidelity_c64": float(abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real))}
 
 
+def event_time(stream, torch, fn) -> float:
+    """Seconds between HIP events recorded around fn() on `stream`."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3
+
+
+TABLE2 = [(10, 5), (11, 8), (12, 6), (13, 12), (14, 6), (15, 3)]  # (address, data) qubits
+
+
+def qcrank_table2(qg, W, torch):
+    """QCrank image encoding at Table 2's shapes (m address + d data qubits, 2^m d pixels =
+    CX gates, 3000 * 2^m shots; synthetic pixels): the encoding circuit and the shot draw
+    timed separately, complex128, greedy fusion."""
+    stream = torch.cuda.current_stream()
+    out = {}
+    for m, nd in TABLE2:
+        circ, _ = W.config2(seed=W.SEED_BASE + 20 + m, n_addr=m, n_data=nd)
+        n = m + nd
+        st = qg.State(n, "c128")
+        st.apply(circ, qg.FUSE_GREEDY)  # warm-up
+        st.reset()
+        t_apply = event_time(stream, torch, lambda: st.apply(circ, qg.FUSE_GREEDY))
+        shots = 3000 << m
+        st.sample(1000, 1)
+        t_shots = min(event_time(stream, torch, lambda: st.sample(shots, W.SEED_BASE + r)) for r in range(2))
+        _, npass = qg.plan_passes(circ, "c128", qg.FUSE_GREEDY)
+        out[f"m{m}_d{nd}"] = {"qubits": n, "pixels": nd << m, "gates": circ.n_gates, "passes": npass,
+                              "t_apply_ms": round(t_apply * 1e3, 3),
+                              "amp_updates_per_s": circ.n_gates * (1 << n) / t_apply,
+                              "shots": shots, "t_shots_ms": round(t_shots * 1e3, 3), "shots_per_s": shots / t_shots}
+        st.close()
+        torch.cuda.empty_cache()
+    return out
+
+
+def qft_study(qg, W, torch):
+    """The QFT's precision and approximation (Table 1's QFT row, App. D.2's rotation-angle
+    approximation): after a random U3 layer, the exact QFT and versions with every CP of
+    angle below eps dropped, at 30 qubits complex128 and 32 complex64: passes, time, and the
+    fidelity |<exact|approx>|^2 (computed on the GPU in FP64).  Then the complex64 result
+    against the complex128 one for the exact QFT at 16, 24 and 33 qubits."""
+    stream = torch.cuda.current_stream()
+
+    def prep(n):
+        rng = W.SplitMix64(W.SEED_BASE + 60 + n)
+        b = W.CircuitBuilder(n)
+        for q in range(n):
+            b.g1(W.U3, q, *(2 * math.pi * rng.uniform(3)))
+        return b.build()
+
+    def overlap(a, b, chunk=1 << 26):
+        """<a|b>, |a|^2, |b|^2 in FP64 over chunks (either state may be complex64)."""
+        ab = aa = bb = 0.0 + 0j
+        for i in range(0, a.numel(), chunk):
+            x = a[i:i + chunk].to(torch.complex128)
+            y = b[i:i + chunk].to(torch.complex128)
+            ab += complex(torch.vdot(x, y).item())
+            aa += complex(torch.vdot(x, x).item())
+            bb += complex(torch.vdot(y, y).item())
+        return ab, aa.real, bb.real
+
+    out = {"approx": {}, "c64_vs_c128": {}}
+    for n, dt in ((30, "c128"), (32, "c64")):
+        exact = W.qft(n).build()
+        p = prep(n)
+        ref = qg.State(n, dt)
+        ref.apply(p, qg.FUSE_GREEDY)
+        ref.apply(exact, qg.FUSE_GREEDY)
+        st = qg.State(n, dt)
+        rows = {}
+        for k in (0, 16, 12, 8, 6, 4):
+            eps = 0.0 if k == 0 else math.pi / 2 ** k
+            circ = W.prune_small_rotations(exact, eps)
+            st.reset()
+            st.apply(p, qg.FUSE_GREEDY)
+            st.apply(circ, qg.FUSE_GREEDY)  # warm-up
+            st.reset()
+            st.apply(p, qg.FUSE_GREEDY)
+            t = event_time(stream, torch, lambda: st.apply(circ, qg.FUSE_GREEDY))
+            ab, aa, bb = overlap(ref.tensor, st.tensor)
+            _, npass = qg.plan_passes(circ, dt, qg.FUSE_GREEDY)
+            rows["exact" if k == 0 else f"eps_pi_over_2^{k}"] = {
+                "gates": circ.n_gates, "passes": npass, "t_ms": round(t * 1e3, 2),
+                "fidelity": abs(ab) ** 2 / (aa * bb)}
+        out["approx"][f"{n}q_{dt}"] = rows
+        st.close()
+        ref.close()
+        torch.cuda.empty_cache()
+    for n in (16, 24, 33):
+        circ = W.concat(prep(n), W.qft(n).build())
+        a = qg.State(n, "c128")
+        a.apply(circ, qg.FUSE_GREEDY)
+        b = qg.State(n, "c64")
+        b.apply(circ, qg.FUSE_GREEDY)
+        ab, aa, bb = overlap(a.tensor, b.tensor)
+        dmax = 0.0
+        for i in range(0, a.tensor.numel(), 1 << 26):
+            d = (a.tensor[i:i + (1 << 26)] - b.tensor[i:i + (1 << 26)].to(torch.complex128)).abs().max().item()
+            dmax = max(dmax, d)
+        out["c64_vs_c128"][f"{n}q"] = {"gates": circ.n_gates, "max_abs_diff": dmax,
+                                       "one_minus_fidelity": 1.0 - abs(ab) ** 2 / (aa * bb),
+                                       "norm_c64_minus_1": bb - 1.0}
+        a.close()
+        b.close()
+        torch.cuda.empty_cache()
+    return out
+
+
+def cx_block_workloads(qg, W, torch, sizes, blocks_list, fusions, log, shots: int = 3000):
+    """The paper's random CX-block unitaries (Alg. 1; 'short' = 100 blocks, 'long' = 10,000)
+    followed by a 3000-shot draw, at each (qubits, dtype) of `sizes`: apply time, passes,
+    amplitude updates per second, the plan's HBM bytes per second against the 8 TB/s peak,
+    and the shot time, for each fusion mode (greedy width 5, learned)."""
+    stream = torch.cuda.current_stream()
+    out = {}
+    for n, dt in sizes:
+        st = qg.State(n, dt)
+        for blocks in blocks_list:
+            circ = W.cx_blocks(n, blocks, W.SEED_BASE + 70 + blocks)
+            for fusion in fusions:
+                fname = "greedy" if fusion == qg.FUSE_GREEDY else "learned"
+                passes, hbm = qg.plan_bytes(circ, dt, qg.FORM_APPLY, fusion)
+                st.reset()
+                t = event_time(stream, torch, lambda: st.apply(circ, fusion))
+                st.sample(100, 1)
+                ts = event_time(stream, torch, lambda: st.sample(shots, W.SEED_BASE + 71))
+                key = f"{n}q_{dt}_{blocks}blocks_{fname}"
+                out[key] = {"gates": circ.n_gates, "passes": passes, "t_s": round(t, 4),
+                            "amp_updates_per_s": circ.n_gates * (1 << n) / t,
+                            "hbm_frac": round(hbm / t / 1e9 / HBM_PEAK_GBS, 4),
+                            "t_shots_ms": round(ts * 1e3, 3)}
+                log(f"{key}: {out[key]}")
+        st.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_speedup(qg, W, torch):
     """Config 5: gradient of sum <Z_i Z_i+1> (24 qubits, 480 parameters) by one adjoint sweep
     vs the plain method, central differences (960 forward simulations + expectations)."""
@@ -217,8 +362,10 @@ def adjoint_speedup(qg, W, torch):
     st.apply(circ, qg.FUSE_GREEDY)
     t_fd, _ = timed(plain, torch.cuda.synchronize)
     st.close()
+    passes, hbm = qg.plan_bytes(circ, "c128", qg.FORM_ADJOINT)
     return {"workload": "24 qubits c128, 10-layer ansatz, 480 parameters, 710 gates",
             "t_adjoint_s": round(t_adj, 4), "t_plain_fd_s": round(t_fd, 3),
+            "passes": passes, "hbm_bytes": hbm, "hbm_frac": round(hbm / t_adj / 1e9 / HBM_PEAK_GBS, 4),
             "plain": "central differences, 960 greedy-fused forward passes + expval",
             "speedup": round(t_fd / t_adj, 1)}
 
@@ -236,8 +383,13 @@ def batched_speedup(qg, W, torch):
             b.launch()
             t_b, _ = timed(b.launch, stream.synchronize)
             b.close()
+            hbm = sum(qg.plan_bytes(c, dtype, qg.FORM_BATCHED)[1] for c in circs)
             out[f"t_batched_{dtype}_s"] = round(t_b, 4)
             out[f"amp_updates_per_s_batched_{dtype}"] = amp_updates / t_b
+            # circuits above one tile stream a scratch state (L2 / Infinity Cache
+            # may serve part of it): these are the bytes they move, at most
+            out[f"scratch_bytes_{dtype}"] = hbm
+            out[f"hbm_frac_{dtype}"] = round(hbm / t_b / 1e9 / HBM_PEAK_GBS, 4)
         states = {}
         for n in sorted({c.n_qubits for c in circs}):
             states[n] = qg.State(n, "c128", stream=stream)
@@ -259,28 +411,44 @@ def batched_speedup(qg, W, torch):
     return out
 
 
-def learned_gain(qg, W, torch, samples, log):
-    """Cost model trained on pass timings the simulator makes (library MLP kernels), then
-    measured time of greedy width-5 plans vs learned plans on held-out circuits."""
+def train_cost_model(qg, samples, log):
+    """Cost model trained on pass timings the simulator makes (library MLP kernels):
+    (model, info)."""
     from paper_2504_03967_amd import costmodel as cm
     t0 = time.perf_counter()
-    X, y = cm.collect(samples, n_values=(20, 22, 24, 26, 28), log=log)
+    X, y = cm.collect(samples, n_values=(20, 22, 24, 26, 28, 30, 32), log=log)
     t_collect = time.perf_counter() - t0
     n_train = int(0.85 * len(y))
     t1 = time.perf_counter()
     model, losses = cm.train(X[:n_train], y[:n_train], epochs=300, batch=128, lr=2e-3)
     t_train = time.perf_counter() - t1
     err = cm.mape(model, X[n_train:], y[n_train:])
+    return model, {"samples": int(len(y)), "t_collect_s": round(t_collect, 1), "t_train_s": round(t_train, 2),
+                   "train_loss_first_last": [round(float(losses[0]), 4), round(float(losses[-1]), 4)],
+                   "heldout_mape": round(err, 3)}
+
+
+def learned_gain(qg, W, torch, samples, log):
+    """Measured time of greedy width-5 plans vs learned plans: 20 held-out CX-block / QFT
+    circuits (20-30 qubits) and config 3 at 28 qubits (also against the unfused plain
+    method), five alternating repeats each for the spread."""
+    from paper_2504_03967_amd import costmodel as cm
+    model, info = train_cost_model(qg, samples, log)
     model.install()
     circs = cm.held_out_circuits(count=20)
-    res = cm.compare_plans(circs)
+    res = cm.compare_plans(circs, reps=1, repeats=5)
+    c3 = cm.compare_plans([W.config3(28)], reps=1, repeats=5, unfused=True)
     qg.clear_cost_model()
     model.close()
-    return {"samples": int(len(y)), "t_collect_s": round(t_collect, 1), "t_train_s": round(t_train, 2),
-            "train_loss_first_last": [round(float(losses[0]), 4), round(float(losses[-1]), 4)],
-            "heldout_mape": round(err, 3), "circuits": len(circs),
+    return {**info, "circuits": len(circs),
             "t_greedy5_s": round(res["t_greedy_s"], 4), "t_learned_s": round(res["t_learned_s"], 4),
-            "gain": round(res["gain"], 3)}
+            "gain": round(res["gain"], 3), "gain_range_5_repeats": [round(res["gain_min"], 3), round(res["gain_max"], 3)],
+            "greedy_spread": round(res["greedy_spread"], 4),
+            "config3_28q": {"t_greedy5_s": round(c3["t_greedy_s"], 4), "t_learned_s": round(c3["t_learned_s"], 4),
+                            "t_unfused_s": round(c3["t_unfused_s"], 3), "gain": round(c3["gain"], 3),
+                            "gain_range_5_repeats": [round(c3["gain_min"], 3), round(c3["gain_max"], 3)],
+                            "gain_vs_unfused": round(c3["gain_vs_unfused"], 2)},
+            "gain_config3": round(c3["gain"], 3)}
 
 
 def log(msg):
@@ -321,6 +489,37 @@ def main():
     if args.config3_only:
         print(json.dumps({"config3": config3_timing(qg, W, torch, args.config3_only)}), flush=True)
         return
+    if args.form_only == "adjoint":
+        circ = W.config5()
+        masks = W.zz_chain_masks(circ.n_qubits)
+        for _ in range(2):
+            t, _ = timed(lambda: qg.adjoint_grad(circ, masks, np.ones(masks.size), circ.n_params),
+                         torch.cuda.synchronize)
+        passes, hbm = qg.plan_bytes(circ, "c128", qg.FORM_ADJOINT)
+        print(json.dumps({"adjoint": {"t_s": round(t, 5), "passes": passes, "hbm_bytes": hbm,
+                                      "hbm_frac": round(hbm / t / 1e9 / HBM_PEAK_GBS, 4)}}), flush=True)
+        return
+    if args.form_only == "batched":
+        circs = W.config4()
+        out = {}
+        for dtype in ("c128", "c64"):
+            b = qg.Batch(circs, dtype)
+            b.launch()
+            t, _ = timed(b.launch, torch.cuda.synchronize)
+            b.close()
+            out[dtype] = {"t_s": round(t, 5),
+                          "scratch_bytes": sum(qg.plan_bytes(c, dtype, qg.FORM_BATCHED)[1] for c in circs)}
+        print(json.dumps({"batched": out}), flush=True)
+        return
+    if args.paper_workloads:
+        model = train_cost_model(qg, args.cm_samples, log)[0]
+        model.install()
+        res = cx_block_workloads(qg, W, torch, [(28, "c128"), (30, "c128"), (32, "c128"), (34, "c64")],
+                                 (100, 10000), (qg.FUSE_GREEDY, qg.FUSE_LEARNED), log)
+        qg.clear_cost_model()
+        model.close()
+        print(json.dumps({"cx_block_workloads": res}), flush=True)
+        return
     n = args.n
     amp_bytes = 16 if args.dtype == "c128" else 8
     from paper_2504_03967_amd import autotune
@@ -341,7 +540,7 @@ def main():
         del src, dst
 
     def modes(name):
-        return qg.FUSE_GREEDY if name.startswith("fused") else qg.FUSE_NONE
+        return qg.FUSE_GREEDY if name.startswith(("fused", "dense")) else qg.FUSE_NONE
 
     events = []
 
@@ -401,6 +600,17 @@ def main():
     for name, _ in parts:
         if not name.startswith("u3"):
             sweep[name + "_GBps"] = round(algo_frac(name) * pass_bytes / float(np.mean(per[name])) / 1e9, 1)
+    # Dense blocks are dense complex products on the matrix cores: 8 2^(n + k) flops for a
+    # k-qubit block (4 real products of 2^k x 2^k by 2^k x 2^(n - k)), against the MFMA peak
+    # of the precision (FP64 78.6 TFLOP/s for complex128, FP32 157.3 for complex64).
+    mfma_peak = 78.6 if args.dtype == "c128" else 157.3
+    for name, c in parts:
+        if name.startswith("dense_k"):
+            k = int(name[-1])
+            tf = 8.0 * 2.0 ** (n + k) / float(np.mean(per[name])) / 1e12
+            sweep[name + "_TFLOPs"] = round(tf, 2)
+            sweep[name + "_mfma_frac"] = round(tf / mfma_peak, 4)
+            sweep[name + "_hbm_frac"] = round(sweep[name + "_GBps"] / HBM_PEAK_GBS, 4)
     # Dominant kernel: the tile pass.  The planner sends standalone SWAPs to the permutation
     # kernels and single gates with their target inside a cache line to the lane kernel; those
     # parts stay out of the tile-pass figure.
@@ -447,6 +657,12 @@ def main():
         extras["config3"] = config3_timing(qg, W, torch)
         log("QFT and random CX-block unitaries (30 qubits c128)")
         extras["paper_shaped"] = paper_shaped(qg, W, torch)
+        extras["paper_shaped"]["cx_blocks"] = cx_block_workloads(qg, W, torch, [(30, "c128")], (100, 1000),
+                                                                 (qg.FUSE_GREEDY,), log)
+        log("QCrank at Table 2 shapes")
+        extras["qcrank_table2"] = qcrank_table2(qg, W, torch)
+        log("QFT precision and approximation")
+        extras["qft_study"] = qft_study(qg, W, torch)
         log("large shot counts; complex64 vs complex128")
         extras["large_shots"] = large_shots(qg, W, torch)
         extras["precision"] = precision_gap(qg, W, torch)
@@ -472,7 +688,8 @@ def main():
         "dtype": "f64" if args.dtype == "c128" else "f32",
         "data": "synthetic",
         "config": {"workload": f"gate sweep, {n} qubits {args.dtype}: U3 x{n} targets, CX/CP/SWAP x5 pairs, "
-                               f"fused U3 groups k=2..6, then probs(1024), 10^4 shots, {n - 1} ZZ expvals",
+                               f"fused U3 groups k=2..6, dense blocks of 48 / 64 gates on 5 / 6 qubits, "
+                               f"then probs(1024), 10^4 shots, {n - 1} ZZ expvals",
                    "n_qubits": n, "gates_per_step": gates_per_step, "state_GiB": (1 << n) * amp_bytes / 2 ** 30},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -89,7 +89,7 @@ def time_apply(st: "qg.State", circ: W.Circuit, fusion: int, reps: int = 3) -> f
     return float(np.median([a.elapsed_time(b) for a, b in ts])) * 1e-3
 
 
-def collect(n_samples: int, n_values: Sequence[int] = (20, 22, 24, 26, 28),
+def collect(n_samples: int, n_values: Sequence[int] = (20, 22, 24, 26, 28, 30, 32),
             dtypes: Sequence[str] = ("c128", "c64"), seed: int = W.SEED_BASE + 5, reps: int = 3,
             log=None) -> Tuple[np.ndarray, np.ndarray]:
     """(X [N, 24] float32 features, y [N] float32 = ln(us)) of timed random passes."""
@@ -115,8 +115,9 @@ def collect(n_samples: int, n_values: Sequence[int] = (20, 22, 24, 26, 28),
             states[key].apply(W.uniform_superposition(n), qg.FUSE_GREEDY)
         prev = set_config(dtype, 3 if k == qg.PASS_DENSE else k)
         prev_dense = qg.get_tuning("dense_min_gates")
-        if k == qg.PASS_DENSE:
-            qg.set_tuning("dense_min_gates", 1)
+        # the sample runs as the strategy its features name: a dense block, or a tile
+        # pass even where the planner's own threshold would pick a dense block
+        qg.set_tuning("dense_min_gates", 1 if k == qg.PASS_DENSE else 1 << 30)
         try:
             t = time_apply(states[key], block, qg.FUSE_GREEDY, reps)
         finally:
@@ -159,21 +160,41 @@ def held_out_circuits(count: int = 20, seed: int = W.SEED_BASE + 6, n_values=(20
     return out
 
 
-def compare_plans(circs: List[W.Circuit], dtype: str = "c128", reps: int = 3) -> Dict[str, float]:
-    """Measured time of greedy-5 vs learned plans (the installed model) on the same circuits."""
-    tg = tl = 0.0
+def compare_plans(circs: List[W.Circuit], dtype: str = "c128", reps: int = 3, repeats: int = 1,
+                  unfused: bool = False) -> Dict[str, object]:
+    """Measured time of greedy-5 vs learned plans (the installed model) on the same circuits,
+    summed over the circuits, `repeats` times in alternation (greedy, learned, greedy, ...),
+    so that the spread of the totals shows the run-to-run noise; optionally the unfused plain
+    method (one pass per gate) once."""
     states: Dict[int, qg.State] = {}
     rows = []
+    tg = np.zeros(repeats)
+    tl = np.zeros(repeats)
+    tn = 0.0
     for c in circs:
         if c.n_qubits not in states:
             states[c.n_qubits] = qg.State(c.n_qubits, dtype)
         st = states[c.n_qubits]
-        g = time_apply(st, c, qg.FUSE_GREEDY, reps)
-        l = time_apply(st, c, qg.FUSE_LEARNED, reps)
+        g = np.zeros(repeats)
+        l = np.zeros(repeats)
+        for r in range(repeats):
+            g[r] = time_apply(st, c, qg.FUSE_GREEDY, reps)
+            l[r] = time_apply(st, c, qg.FUSE_LEARNED, reps)
         tg += g
         tl += l
+        if unfused:
+            tn += time_apply(st, c, qg.FUSE_NONE, 1)
         rows.append((c.n_qubits, c.n_gates, qg.plan_passes(c, dtype, qg.FUSE_GREEDY)[1],
-                     qg.plan_passes(c, dtype, qg.FUSE_LEARNED)[1], g, l))
+                     qg.plan_passes(c, dtype, qg.FUSE_LEARNED)[1], float(np.median(g)), float(np.median(l))))
     for st in states.values():
         st.close()
-    return {"t_greedy_s": tg, "t_learned_s": tl, "gain": tg / tl, "rows": rows}
+    gains = tg / tl
+    out = {"t_greedy_s": float(np.median(tg)), "t_learned_s": float(np.median(tl)),
+           "gain": float(np.median(tg) / np.median(tl)),
+           "gain_min": float(gains.min()), "gain_max": float(gains.max()),
+           # run-to-run spread of the same plan: relative range of the greedy totals
+           "greedy_spread": float((tg.max() - tg.min()) / np.median(tg)), "rows": rows}
+    if unfused:
+        out["t_unfused_s"] = tn
+        out["gain_vs_unfused"] = tn / float(np.median(tl))
+    return out

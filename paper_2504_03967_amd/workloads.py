@@ -363,7 +363,7 @@ def config5(seed: int = SEED_BASE + 4, n: int = 24, layers: int = 10) -> Circuit
 
 
 SWEEP_PAIRS = ((0, 1), (1, 29), (29, 0), (15, 16), (28, 29))
-SWEEP_DENSE_GATES = 48
+SWEEP_DENSE_GATES = {5: 48, 6: 64}
 
 
 def sweep(n: int = 30, seed: int = SEED_BASE + 0) -> Tuple[Circuit, Circuit, List[Tuple[str, Circuit]]]:
@@ -371,7 +371,7 @@ def sweep(n: int = 30, seed: int = SEED_BASE + 0) -> Tuple[Circuit, Circuit, Lis
     U3 on every qubit; ``parts`` are the timed pieces: U3 on each target t = 0..n-1, then
     CX, CP and SWAP on each pair of ``SWEEP_PAIRS`` (scaled into range for n < 30), then
     a k-gate group of U3 on k distinct random qubits for k = 2..6, then blocks of
-    SWEEP_DENSE_GATES random gates on 5 and on 6 of the pair qubits (dense-block passes).
+    SWEEP_DENSE_GATES[k] random gates on k = 5 and 6 of the pair qubits (dense-block passes).
     ``full`` concatenates the parts."""
     rng = SplitMix64(seed)
     pb = CircuitBuilder(n)
@@ -398,13 +398,13 @@ def sweep(n: int = 30, seed: int = SEED_BASE + 0) -> Tuple[Circuit, Circuit, Lis
         for q in qs:
             cb.g1(U3, q, *(2 * math.pi * rng.uniform(3)))
         parts.append((f"fused_k{k}", cb.build()))
-    # dense blocks: SWEEP_DENSE_GATES random gates (all ten ops) on 5 and on 6 of the
-    # qubits the pairs above already entangle
+    # dense blocks: SWEEP_DENSE_GATES[k] random gates (all ten ops) on k = 5 and 6 of
+    # the qubits the pairs above already entangle
     ent = sorted({q for ab in pairs for q in ab})
     for k in (5, 6):
         qs = ent[:k] if k < len(ent) else ent
         cb = CircuitBuilder(n)
-        for _ in range(SWEEP_DENSE_GATES):
+        for _ in range(SWEEP_DENSE_GATES[k]):
             op = int(rng.below(10)[0])
             t = qs[int(rng.below(len(qs))[0])]
             c = -1

@@ -47,5 +47,7 @@ def test_learned_plan_parity_and_time(trained):
             for q in ((q0, q1) if op in W.TWO_QUBIT else (q1,)):
                 assert q not in last or pog[last[q]] <= pog[i]
                 last[q] = i
-    res = cm.compare_plans([c for c in circs if c.n_qubits == 20])
-    assert res["gain"] > 0.8, res
+    # learned plans must not be slower than greedy beyond the run-to-run spread of the
+    # greedy plan itself (five alternating repeats of the same circuits)
+    res = cm.compare_plans([c for c in circs if c.n_qubits == 20], reps=1, repeats=5)
+    assert res["gain"] >= 1.0 - 2.0 * res["greedy_spread"] - 0.01, res

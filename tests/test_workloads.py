@@ -65,7 +65,7 @@ def test_sweep_parts():
     assert prep.n_gates == 30
     names = [p[0] for p in parts]
     assert names[:30] == [f"u3_t{t}" for t in range(30)]
-    assert sum(c.n_gates for _, c in parts) == full.n_gates == 30 + 15 + sum(range(2, 7)) + 2 * W.SWEEP_DENSE_GATES
+    assert sum(c.n_gates for _, c in parts) == full.n_gates == 30 + 15 + sum(range(2, 7)) + sum(W.SWEEP_DENSE_GATES.values())
     # the dense blocks stay on the qubits the CX / CP / SWAP pairs already entangle
     pair_qubits = {q for a, b in W.SWEEP_PAIRS for q in (a, b)}
     for name, c in parts[-2:]:
