@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2504_03967_amd/csrc/qg_tile_dev.h", "paper_2504_03967_amd/csrc/qg_tile.hip",
                   "paper_2504_03967_amd/csrc/qg_plan.cpp", "paper_2504_03967_amd/csrc/qg_internal.h",
                   "paper_2504_03967_amd/csrc/qg_api.cpp")
-MEASURED_TRAFFIC = {"sources": "066cae024e0531af", "traffic_over_algorithmic": 1.00062}
+MEASURED_TRAFFIC = {"sources": "1689afadfe64d75c", "traffic_over_algorithmic": 1.00077}
 
 
 def kernel_sources_hash() -> str:
@@ -573,6 +573,10 @@ def main():
     gates_per_step = full.n_gates
     amp_updates = gates_per_step * (1 << n) * args.steps
     value = amp_updates / elapsed
+    dense_names = [nm for nm, _ in parts if nm.startswith("dense")]
+    dense_gates = sum(c.n_gates for nm, c in parts if nm in dense_names)
+    dense_time = sum(e0.elapsed_time(e1) * 1e-3 for nm, e0, e1 in events if nm in dense_names)
+    value_nodense = (gates_per_step - dense_gates) * (1 << n) * args.steps / (elapsed - dense_time)
 
     per = {}
     for name, e0, e1 in events:
@@ -692,6 +696,9 @@ def main():
                                f"then probs(1024), 10^4 shots, {n - 1} ZZ expvals",
                    "n_qubits": n, "gates_per_step": gates_per_step, "state_GiB": (1 << n) * amp_bytes / 2 ** 30},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+        # the same step without its two dense-block parts (112 of its gates), for
+        # comparison with sweeps that have none
+        "value_without_dense_parts": value_nodense,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_tile_inl (tile pass)", "launches_per_step": len(tile_parts),
