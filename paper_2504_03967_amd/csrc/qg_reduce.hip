@@ -308,17 +308,34 @@ __global__ void k_apply_observable(const typename V2<R>::T *__restrict__ psi, ty
     }
 }
 
-// One wave per row: lanes sum strided partials, then a butterfly sum.
-__global__ void k_grad_rows(const double *__restrict__ gpart, int64_t gstride, int64_t count, int n_rows,
-                            double *__restrict__ rows) {
-    const int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
+// One block of kGradThreads per row: each thread sums a strided quarter of the
+// row into four accumulators (independent loads in flight), then waves and the
+// block combine in a fixed order, so a row's sum does not depend on timing.
+constexpr int kGradThreads = 1024;
+__global__ void __launch_bounds__(kGradThreads) k_grad_rows(const double *__restrict__ gpart, int64_t gstride,
+                                                            int64_t count, int n_rows, double *__restrict__ rows) {
+    __shared__ double wsum[kGradThreads / 64];
+    const int r = blockIdx.x;
+    const int tid = threadIdx.x;
     if (r >= n_rows) return;
-    double s = 0.0;
     const double *p = gpart + (int64_t)r * gstride;
-    for (int64_t k = lane; k < count; k += 64) s += p[k];
-    s = wave_sum(s);
-    if (lane == 0) rows[r] = s;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t k = tid;
+    for (; k + 3 * kGradThreads < count; k += 4 * kGradThreads) {
+        s0 += p[k];
+        s1 += p[k + kGradThreads];
+        s2 += p[k + 2 * kGradThreads];
+        s3 += p[k + 3 * kGradThreads];
+    }
+    for (; k < count; k += kGradThreads) s0 += p[k];
+    double s = wave_sum((s0 + s1) + (s2 + s3));
+    if ((tid & 63) == 0) wsum[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kGradThreads / 64; ++w) t += wsum[w];
+        rows[r] = t;
+    }
 }
 
 __global__ void k_grad_slots(const double *__restrict__ rows, const int32_t *__restrict__ slot, int n_rows,
@@ -510,8 +527,7 @@ hipError_t launch_apply_observable(bool c64, const void *psi, void *lam, uint64_
 hipError_t launch_grad_rows(const double *gpart, int64_t gstride, int64_t count, int n_rows, double *rows,
                             hipStream_t st) {
     if (n_rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_grad_rows, dim3((n_rows * 64 + 255) / 256), dim3(256), 0, st, gpart, gstride, count, n_rows,
-                       rows);
+    hipLaunchKernelGGL(k_grad_rows, dim3(n_rows), dim3(kGradThreads), 0, st, gpart, gstride, count, n_rows, rows);
     return hipGetLastError();
 }
 
