@@ -178,13 +178,16 @@ qg_status qg_adjoint_grad(const qg_circuit *c, qg_dtype dtype, const uint64_t *z
 
 /* Batched form (the paper's parallel / multi-circuit mode, Sec. 2.4): n_circ
  * independent circuits of possibly different qubit counts (1..22), each from
- * |0...0>, run by one persistent launch; out[c] = sum_{i<n_c-1} <Z_i Z_{i+1}> of
- * circuit c (obs_kind QG_OBS_ZZ_CHAIN), or sum over its CSR terms
- * k in [obs_off[c], obs_off[c+1]) of coeff[k] <Z_{zmask[k]}> (QG_OBS_CSR; host
- * arrays, obs_off has n_circ + 1 entries starting at 0).  Circuits whose state
- * fits one tile (2^12 amplitudes in complex128, 2^13 in complex64) never
- * touch HBM; larger ones use a per-workgroup scratch state.  out: device
- * [n_circ] (written when the launch runs). */
+ * |0...0>; out[c] = sum_{i<n_c-1} <Z_i Z_{i+1}> of circuit c (obs_kind
+ * QG_OBS_ZZ_CHAIN), or sum over its CSR terms k in [obs_off[c], obs_off[c+1])
+ * of coeff[k] <Z_{zmask[k]}> (QG_OBS_CSR; host arrays, obs_off has n_circ + 1
+ * entries starting at 0).  Circuits whose state fits one tile (2^12 amplitudes
+ * in complex128, 2^13 in complex64) run in one persistent launch and never
+ * touch device memory; larger ones keep their states in device memory (at
+ * most 32 GiB or half the free memory at a time, in groups) and run pass by
+ * pass, one launch per pass index for all circuits of a group.  out: device
+ * [n_circ] (written when the launch runs; each value is a fixed-order sum, the
+ * same on every launch). */
 typedef enum { QG_OBS_ZZ_CHAIN = 0, QG_OBS_CSR = 1 } qg_obs_kind;
 
 /* One-shot: plan, upload, launch, release (the release waits for the stream). */
@@ -192,12 +195,13 @@ qg_status qg_batch_expval(const qg_circuit *circs, int n_circ, qg_dtype dtype, i
                           const int64_t *obs_off, const uint64_t *zmask, const double *coeff,
                           void *hip_stream, double *out);
 
-/* Reusable batch: qg_batch_create plans and uploads every circuit, allocates the
- * scratch states and, when hip_stream is not the NULL stream, captures the
- * launch into a HIP graph; qg_batch_launch replays it (or launches directly) on
- * that stream.  qg_batch_set_params uploads new angles for circuits with the
- * same gate structure (codes and qubits; QG_EINVAL otherwise), enqueued on the
- * stream before the next launch.  qg_batch_free waits for the stream. */
+/* Reusable batch: qg_batch_create plans and uploads every circuit, allocates
+ * the device states of its multi-tile circuits and, when hip_stream is not the
+ * NULL stream, captures the launches into a HIP graph; qg_batch_launch replays
+ * it (or launches directly) on that stream.  qg_batch_set_params uploads new
+ * angles for circuits with the same gate structure (codes and qubits;
+ * QG_EINVAL otherwise), enqueued on the stream before the next launch.
+ * qg_batch_free waits for the stream. */
 typedef struct qg_batch qg_batch;
 qg_status qg_batch_create(const qg_circuit *circs, int n_circ, qg_dtype dtype, int obs_kind,
                           const int64_t *obs_off, const uint64_t *zmask, const double *coeff,
@@ -240,8 +244,10 @@ qg_status qg_plan_kernels(const qg_circuit *c, qg_dtype dtype, int fusion_mode,
  *                    both states (fusion_mode ignored);
  *   QG_FORM_BATCHED  one circuit of qg_batch_expval (fusion_mode ignored): 0 for
  *                    a circuit whose state fits one tile (registers and LDS
- *                    only), else its scratch state initialised, streamed once
- *                    per pass and read by the observable (n_qubits <= 22).
+ *                    only), else its state in device memory streamed once per
+ *                    pass (the first pass writes it without reading it, unless
+ *                    the pass skips tiles and the state is filled first) and
+ *                    read once by the observable (n_qubits <= 22).
  * Either output may be NULL.  Errors: QG_EINVAL for an invalid circuit, dtype,
  * form or fusion mode. */
 typedef enum { QG_FORM_APPLY = 0, QG_FORM_ADJOINT = 1, QG_FORM_BATCHED = 2 } qg_form;

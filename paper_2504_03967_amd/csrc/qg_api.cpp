@@ -298,20 +298,21 @@ struct qg_state {
 namespace {
 
 constexpr int kBatchMaxQubits = 22;
+// Tile of the batched kernels: a state of at most this many qubits lives in one
+// workgroup's registers and LDS.
+inline int batch_tile_bits(bool c64) { return c64 ? 13 : 12; }
 
 PlanConfig batch_config(int n, bool c64) {
     PlanConfig cfg = default_config(n, c64, QG_FUSE_GREEDY);
-    cfg.tile_bits = c64 ? 13 : 12;
+    cfg.tile_bits = batch_tile_bits(c64);
     cfg.reg_bits = c64 ? 5 : 4;
     cfg.low_bits = c64 ? 8 : 7;
     cfg.max_high = 5;
-    cfg.flags = 0;       // states are re-read by the same workgroup: keep them cacheable
     cfg.swz_bits = 0;
     cfg.max_gates_per_pass = n <= cfg.tile_bits ? (1 << 30) : 4096;
     cfg.use_classes = false;  // the persistent kernel is built for one register width
     cfg.diag_run_min = 0;     // its programs carry no fused diagonal runs
     cfg.dense_min_gates = 1 << 30;  // nor dense blocks
-    cfg.half_lds = false;     // its LDS is sized for whole complex values; registers limit occupancy
     clamp_config(&cfg);
     return cfg;
 }
@@ -377,14 +378,19 @@ qg_status batch_build(qg_batch *b, const qg_circuit *circs, const int64_t *obs_o
     std::vector<PhaseDesc> phases;
     std::vector<DevOp> ops;
     std::vector<double> cost(nc);
-    int n_big = 0, n_big_count = 0;
-    const int tile_bits = b->c64 ? 13 : 12;
+    std::vector<char> one_tile(nc, 0), needs_fill(nc, 0);
+    int n_big = 0;
+    const int tile_bits = batch_tile_bits(b->c64);
+    const size_t amp = b->c64 ? 8 : 16;
     b->rb = b->c64 ? 5 : 4;
     for (int c = 0; c < nc; ++c) {
         const qg_circuit &q = circs[c];
         Program prog = plan_batch_circuit(q, b->c64);
         for (PassDesc &pd : prog.passes) {
             if (pd.rb != b->rb) return fail(QG_EINTERNAL, "batched plan with %d register bits", pd.rb);
+            if ((pd.flags & (PASS_DENSE | PASS_SWAP2 | PASS_SWAPL | PASS_LANE1)) || pd.tb > 8)
+                return fail(QG_EINTERNAL, "batched plan with a pass the batched kernels do not run");
+            pd.flags &= ~PASS_PIPE;  // one workgroup per tile here
             pd.phase_begin += (int)phases.size();
         }
         for (PhaseDesc &ph : prog.phases) {
@@ -396,22 +402,117 @@ qg_status batch_build(qg_batch *b, const qg_circuit *circs, const int64_t *obs_o
         bc[c].n_pass = (int)prog.passes.size();
         bc[c].obs_begin = obs_off ? (int32_t)obs_off[c] : 0;
         bc[c].obs_count = obs_off ? (int32_t)(obs_off[c + 1] - obs_off[c]) : 0;
-        const bool one_tile = bc[c].n_pass == 1 && prog.passes[0].n_tiles == 1;
-        cost[c] = one_tile ? (double)(1ull << q.n_qubits) * (1 + q.n_gates) * 1e-3
-                           : (double)(1ull << q.n_qubits) * (bc[c].n_pass + 2);
-        if (!one_tile) {
+        // One tile holds the whole state (a pass of a larger state may also
+        // visit a single tile when it skips the others).
+        one_tile[c] = std::max(q.n_qubits, b->rb) <= tile_bits;
+        if (one_tile[c] && (bc[c].n_pass != 1 || prog.passes[0].n_tiles != 1))
+            return fail(QG_EINTERNAL, "one-tile batched circuit %d planned in %d passes", c, bc[c].n_pass);
+        if (!one_tile[c]) {
+            if (q.n_qubits < tile_bits || prog.passes[0].b != tile_bits)
+                return fail(QG_EINTERNAL, "multi-tile batched circuit %d with %d-qubit tiles", c, prog.passes[0].b);
+            // a first pass that skips tiles leaves them unwritten: fill |0...0> first
+            needs_fill[c] = prog.passes[0].fixed_mask != 0;
             n_big = std::max(n_big, q.n_qubits);
-            n_big_count++;
         }
+        cost[c] = (double)(1ull << q.n_qubits) * (1 + q.n_gates);
         passes.insert(passes.end(), prog.passes.begin(), prog.passes.end());
         phases.insert(phases.end(), prog.phases.begin(), prog.phases.end());
         ops.insert(ops.end(), prog.ops.begin(), prog.ops.end());
         b->shape.push_back({q.n_qubits, q.n_gates, b->gate_rows.size()});
         b->gate_rows.insert(b->gate_rows.end(), q.gate_type, q.gate_type + 3 * q.n_gates);
     }
-    std::vector<int32_t> order(nc);
-    for (int c = 0; c < nc; ++c) order[c] = c;
+    // One-tile circuits: the persistent launch, longest first.
+    std::vector<int32_t> order;
+    for (int c = 0; c < nc; ++c)
+        if (one_tile[c]) order.push_back(c);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+
+    // Multi-tile circuits, largest state first, in groups whose states fit the
+    // state buffer together.  States are powers of two in decreasing size, so
+    // each starts at a multiple of its own size.
+    std::vector<int32_t> big;
+    for (int c = 0; c < nc; ++c)
+        if (!one_tile[c]) big.push_back(c);
+    std::stable_sort(big.begin(), big.end(), [&](int x, int y) {
+        if (bc[x].n != bc[y].n) return bc[x].n > bc[y].n;
+        return needs_fill[x] > needs_fill[y];
+    });
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = size_t(8) << 30;
+    const size_t largest = big.empty() ? 0 : (amp << bc[big[0]].n);
+    const size_t budget = std::max(largest, std::min(free_b / 2, size_t(32) << 30));
+    std::vector<BatchItem> items;
+    std::vector<BatchChunkItem> chunks;
+    std::vector<int32_t> map;
+    std::vector<BatchObsSum> sums;
+    std::vector<BatchStep> steps;
+    uint64_t n_partial = 0;
+    size_t state_bytes = 0;
+    auto add_chunk_step = [&](int kind, const std::vector<int32_t> &cs, const std::vector<uint64_t> &off) {
+        BatchStep s{};
+        s.kind = kind;
+        s.map_off = map.size();
+        s.partial_off = n_partial;
+        for (size_t k = 0; k < cs.size(); ++k) {
+            const int c = cs[k];
+            const uint64_t nch = (1ull << bc[c].n) / kBatchChunk;
+            BatchChunkItem it{s.blocks, off[k], c, bc[c].n};
+            if (kind == BATCH_OBS) sums.push_back({n_partial + s.blocks, (int32_t)nch, c});
+            map.insert(map.end(), nch, (int32_t)chunks.size());
+            chunks.push_back(it);
+            s.blocks += nch;
+        }
+        if (kind == BATCH_OBS) n_partial += s.blocks;
+        if (s.blocks) steps.push_back(s);
+    };
+    for (size_t g0 = 0; g0 < big.size();) {
+        std::vector<int32_t> grp;
+        std::vector<uint64_t> off;
+        size_t bytes = 0;
+        size_t g1 = g0;
+        for (; g1 < big.size(); ++g1) {
+            const size_t sb = amp << bc[big[g1]].n;
+            if (!grp.empty() && bytes + sb > budget) break;
+            grp.push_back(big[g1]);
+            off.push_back(bytes / amp);
+            bytes += sb;
+        }
+        state_bytes = std::max(state_bytes, bytes);
+        std::vector<int32_t> fill_c;
+        std::vector<uint64_t> fill_off;
+        int max_pass = 0;
+        for (size_t k = 0; k < grp.size(); ++k) {
+            if (needs_fill[grp[k]]) {
+                fill_c.push_back(grp[k]);
+                fill_off.push_back(off[k]);
+            }
+            max_pass = std::max(max_pass, bc[grp[k]].n_pass);
+        }
+        add_chunk_step(BATCH_FILL, fill_c, fill_off);
+        for (int p = 0; p < max_pass; ++p) {
+            BatchStep s{};
+            s.kind = BATCH_PASS;
+            s.map_off = map.size();
+            for (size_t k = 0; k < grp.size(); ++k) {
+                const int c = grp[k];
+                if (p >= bc[c].n_pass) continue;
+                const int pi = bc[c].pass_begin + p;
+                const PassDesc &pd = passes[pi];
+                BatchItem it{s.blocks, off[k], pi, (p == 0 && !needs_fill[c]) ? 1 : 0};
+                map.insert(map.end(), pd.n_tiles, (int32_t)items.size());
+                items.push_back(it);
+                s.blocks += pd.n_tiles;
+                const uint32_t l = pd.n_phase > 1 ? (uint32_t)((size_t(1) << pd.b) *
+                                                               ((pd.flags & PASS_HALFX) ? amp / 2 : amp))
+                                                  : 0u;
+                s.lds = std::max(s.lds, l);
+            }
+            if (s.blocks) steps.push_back(s);
+        }
+        add_chunk_step(BATCH_OBS, grp, off);
+        g0 = g1;
+    }
+    if (map.size() > 0x7fffffffull) return fail(QG_EUNSUPPORTED, "batch too large for the block map");
 
     Pack pk;
     const size_t o_circ = pk.add(bc);
@@ -424,28 +525,28 @@ qg_status batch_build(qg_batch *b, const qg_circuit *circs, const int64_t *obs_o
     const size_t o_coef = pk.add(coeff, n_terms * sizeof(double));
     const int zero = 0;
     const size_t o_cnt = pk.add(&zero, sizeof zero);
+    const size_t o_items = pk.add(items);
+    const size_t o_chunks = pk.add(chunks);
+    const size_t o_map = pk.add(map);
+    const size_t o_sums = pk.add(sums);
+    const size_t o_partial = pk.add(nullptr, 0);
+    pk.bytes.resize(o_partial + n_partial * sizeof(double));
     hipStream_t st = b->cx.stream;
     HIP_TRY(b->dev.buf.ensure(pk.bytes.size(), st), "batch tables");
     b->dev.off_ops = o_ops;
     HIP_TRY(hipMemcpyAsync(b->dev.buf.p, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice, st), "upload batch");
     HIP_TRY(hipStreamSynchronize(st), "upload batch");
     unsigned char *base = static_cast<unsigned char *>(b->dev.buf.p);
+    if (state_bytes) HIP_TRY(b->scratch.ensure(state_bytes, st), "batch states");
 
     int dev_id = 0, n_cu = 256;
     (void)hipGetDevice(&dev_id);
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev_id);
     const int per_cu = 2;
-    int grid = std::max(1, std::min(nc, n_cu * per_cu));
-    const size_t amp = b->c64 ? 8 : 16;
-    uint64_t stride = n_big > 0 ? (1ull << n_big) : 0;
-    if (stride) {
-        // Only as many workgroups as can hold a multi-tile state in flight need a slot.
-        HIP_TRY(b->scratch.ensure((size_t)grid * stride * amp, st), "batch scratch");
-    }
     BatchLaunch &L = b->L;
     L.circs = reinterpret_cast<const BatchCirc *>(base + o_circ);
     L.order = reinterpret_cast<const int32_t *>(base + o_order);
-    L.n_circ = nc;
+    L.n_circ = (int)order.size();
     L.passes = reinterpret_cast<const PassDesc *>(base + o_pass);
     L.phases = reinterpret_cast<const PhaseDesc *>(base + o_phase);
     L.ops = reinterpret_cast<const DevOp *>(base + o_ops);
@@ -453,14 +554,19 @@ qg_status batch_build(qg_batch *b, const qg_circuit *circs, const int64_t *obs_o
     L.coeff = reinterpret_cast<const double *>(base + o_coef);
     L.obs_kind = b->obs_kind;
     L.counter = reinterpret_cast<int *>(base + o_cnt);
-    L.scratch = b->scratch.p;
-    L.scratch_stride = stride;
     L.out = b->out;
-    L.grid = grid;
+    L.grid = std::max(1, std::min(L.n_circ, n_cu * per_cu));
     L.tile_bits = tile_bits;
+    L.items = reinterpret_cast<const BatchItem *>(base + o_items);
+    L.chunks = reinterpret_cast<const BatchChunkItem *>(base + o_chunks);
+    L.map = reinterpret_cast<const int32_t *>(base + o_map);
+    L.sums = reinterpret_cast<const BatchObsSum *>(base + o_sums);
+    L.n_sums = (int)sums.size();
+    L.partial = reinterpret_cast<double *>(base + o_partial);
+    L.states = b->scratch.p;
+    L.steps.swap(steps);
     b->host_ops.swap(ops);
     *n_big_out = n_big;
-    (void)n_big_count;
 
     // Capture reset + persistent kernel once; later launches replay the graph.
     if (st != nullptr && nc > 0) {
@@ -879,12 +985,15 @@ qg_status qg_plan_bytes(const qg_circuit *c, qg_dtype dtype, int form, int fusio
         bytes = state + program_hbm_bytes(fwd, n, c64, 1) + 3.0 * state + program_hbm_bytes(rev, n, c64, 2);
     } else {
         if (n > kBatchMaxQubits) return fail(QG_EINVAL, "n_qubits = %d above the batched form's %d", n, kBatchMaxQubits);
-        Program prog = build_plan(g, batch_config(n, c64));
+        Program prog = plan_batch_circuit(*c, c64);
         np = (int32_t)prog.passes.size();
-        // a state of one tile stays in registers and LDS; a larger one lives in
-        // HBM scratch: initialised, streamed once per pass, read by the observable
-        const bool one_tile = prog.passes.size() == 1 && prog.passes[0].n_tiles == 1;
-        bytes = one_tile ? 0.0 : 2.0 * state + program_hbm_bytes(prog, n, c64, 1);
+        // A state of one tile stays in registers and LDS.  A larger one lives in
+        // device memory: its first pass starts from |0...0> in registers (no
+        // read; a first pass that skips tiles needs the state filled first),
+        // every pass streams it once, and the observable reads it once.
+        const bool one_tile = n <= batch_tile_bits(c64);
+        const bool fill = !one_tile && prog.passes[0].fixed_mask != 0;
+        bytes = one_tile ? 0.0 : program_hbm_bytes(prog, n, c64, 1) + (fill ? 2.0 * state : 0.0);
     }
     if (n_passes) *n_passes = np;
     if (hbm_bytes) *hbm_bytes = bytes;

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/qg.h"
 #include "qg_internal.h"
 
@@ -75,11 +77,48 @@ struct LaneGateArgs {
 };
 hipError_t launch_lane_gate(bool c64, void *psi, int n, const LaneGateArgs &g, bool xcd, hipStream_t st);
 
-// Batched persistent launch (all pointers are device pointers).
+// Batched form.  Circuits whose state is one tile run in one persistent
+// launch, a workgroup per circuit.  Larger circuits run pass by pass: one launch
+// applies the next pass of every such circuit of a group, a workgroup per
+// (circuit, tile), over the group's states in device memory.
+//
+// A workgroup of a multi-tile launch finds its item through the launch's
+// block map: item = items[map[blockIdx.x]], and its tile or chunk within the
+// item is blockIdx.x - item.begin.
+struct BatchItem {
+    uint64_t begin;      // first workgroup of this (circuit, pass) in its launch
+    uint64_t state_off;  // the circuit's state in the state buffer (amplitudes)
+    int32_t pass;        // index into the batch's pass list
+    int32_t zero_init;   // 1: the state is |0...0> before this pass (no loads)
+};
+// kBatchChunk amplitudes of a circuit's state: the unit of the fill and
+// observable kernels.
+constexpr int kBatchChunk = 4096;
+struct BatchChunkItem {
+    uint64_t begin;      // first workgroup of this circuit in its launch
+    uint64_t state_off;
+    int32_t circ;        // index into the batch's circuit list
+    int32_t n;           // qubits (2^n / kBatchChunk chunks)
+};
+// Final sum of one multi-tile circuit's observable partials.
+struct BatchObsSum {
+    uint64_t partial_begin;
+    int32_t count;
+    int32_t circ;
+};
+enum BatchStepKind : int32_t { BATCH_FILL = 0, BATCH_PASS = 1, BATCH_OBS = 2 };
+struct BatchStep {
+    int32_t kind;
+    uint32_t lds;          // dynamic LDS bytes (pass steps)
+    uint64_t blocks;       // workgroups
+    uint64_t map_off;      // first entry of this launch in the block map
+    uint64_t partial_off;  // observable steps: first partial written
+};
 struct BatchLaunch {
+    // one-tile circuits (all pointers are device pointers)
     const BatchCirc *circs;
-    const int32_t *order;       // longest-first processing order
-    int n_circ;
+    const int32_t *order;       // the one-tile circuits, longest first
+    int n_circ;                 // entries of order
     const PassDesc *passes;
     const PhaseDesc *phases;
     const DevOp *ops;
@@ -87,11 +126,18 @@ struct BatchLaunch {
     const double *coeff;
     int obs_kind;
     int *counter;               // work counter (reset by the launch)
-    void *scratch;              // grid * scratch_stride amplitudes for multi-tile circuits
-    uint64_t scratch_stride;    // amplitudes per workgroup slot
     double *out;
     int grid;
     int tile_bits;
+    // multi-tile circuits
+    const BatchItem *items;
+    const BatchChunkItem *chunks;
+    const int32_t *map;
+    const BatchObsSum *sums;
+    int n_sums;
+    double *partial;
+    void *states;
+    std::vector<BatchStep> steps;  // host: launches in stream order
 };
 hipError_t launch_batch(bool c64, int rb, const BatchLaunch &L, hipStream_t st);
 

@@ -18,7 +18,7 @@ using namespace dev;
 // exchanges at three workgroups per CU when it fits 168 registers.
 template <typename R, int RB, int NS>
 struct TileWaves {
-    static constexpr int value = (sizeof(R) == 8 && RB == 4 && NS == 1) ? 3 : 1;
+    static constexpr int value = (sizeof(R) == 8 && ((RB == 4 && NS == 1) || (RB == 3 && NS == 2))) ? 3 : 1;
 };
 
 template <typename R, int RB, int NS>

@@ -1,4 +1,5 @@
-"""Batched persistent launch (config 4 shape) against the oracle, per circuit."""
+"""Batched form (config 4 shape) against the oracle, per circuit: one-tile circuits in the
+persistent launch, larger ones pass by pass."""
 import numpy as np
 import pytest
 import torch
@@ -39,6 +40,32 @@ def test_config4_every_circuit(qg):
         out = qg.batch_expval(circs, dtype).cpu().numpy()
         err = np.abs(out - ref) / terms
         assert np.all(err <= TOL[dtype]), (dtype, int(np.argmax(err)), float(err.max()))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_first_pass_skipping_tiles(qg, dtype):
+    """Multi-tile circuits whose first pass skips tiles (every op of it is conditioned on a
+    qubit outside the tile) start from a filled |0...0>, also in device memory that held
+    another batch's states just before."""
+    lo = 13 if dtype == "c128" else 14
+    amp = 16 if dtype == "c128" else 8
+    junk = W.config4(seed=5, n_circuits=24, n_min=lo, n_max=17, l_min=2, l_max=3)
+    qg.batch_expval(junk, dtype)
+    torch.cuda.synchronize()
+    circs = []
+    for k, n in enumerate(range(lo, lo + 4)):
+        b = W.CircuitBuilder(n)
+        b.g2(W.CP, n - 1, n - 2, 0.3 + k)
+        b.g2(W.CX, n - 1, 0)
+        circs.append(b.build())
+        # one pass over half the tiles (fixed control qubit), after a fill of the state
+        assert qg.plan_bytes(circs[-1], dtype, qg.FORM_BATCHED) == (1, 3.0 * (amp << n))
+    circs += W.config4(seed=6, n_circuits=8, n_min=lo, n_max=lo + 3, l_min=1, l_max=3)
+    out = qg.batch_expval(circs, dtype).cpu().numpy()
+    ref = oracle.batch_zz_chain(circs)
+    terms = np.array([c.n_qubits - 1 for c in circs], dtype=np.float64)
+    err = np.abs(out - ref) / terms
+    assert np.all(err <= TOL[dtype]), (int(np.argmax(err)), float(err.max()))
 
 
 def test_graph_replays_and_new_params(qg):
