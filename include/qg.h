@@ -306,9 +306,12 @@ qg_status qg_set_cost_model(qg_mlp *m);
  *   dense_min_gates                  a run of gates touching <= 6 qubits with at least
  *                                    this many gates runs as one dense MFMA block;
  *                                    0 (default): the break-even measured on MI355X
- *                                    per precision and block width (36 / 36 / 32 gates
- *                                    for 4 / 5 / 6 qubits in complex128, 20 / 20 / 24
+ *                                    per precision and block width (24 / 20 / 28 gates
+ *                                    for 4 / 5 / 6 qubits in complex128, 16 / 16 / 24
  *                                    in complex64); 1 << 30: never
+ *   dense_tile_bits                  tile of a dense block: its k qubits and the
+ *                                    (dense_tile_bits - k) lowest other qubits (10..13,
+ *                                    default 11)
  *   tile_bits_c128 / tile_bits_c64   qubits per tile (amplitudes streamed per workgroup)
  *   reg_bits_c128 / reg_bits_c64     amplitudes per thread = 2^reg_bits
  *   low_bits_c128 / low_bits_c64     lowest qubits kept in every fused tile

@@ -710,7 +710,9 @@ qg_status learned_plan(const std::vector<Gate> &g0, int n, bool c64, PlanEntry *
             if (k == kPlanDense) {
                 j = dense_block_end(g, i, 4096);
                 const uint64_t blk = j > i ? dense_block_qubits(g, i, j, n) : 0;
-                if (!blk) continue;
+                // below the measured break-even a dense block never beats the tile
+                // pass: such candidates would only add room for model error
+                if (!blk || j - i < dense_threshold(cfgs[1], __builtin_popcountll(blk))) continue;
                 cand.push_back({i, j, k});
                 feat.resize(feat.size() + kPlanFeatures);
                 dense_features(g, i, j, blk, cfgs[1], feat.data() + feat.size() - kPlanFeatures);
@@ -719,7 +721,11 @@ qg_status learned_plan(const std::vector<Gate> &g0, int n, bool c64, PlanEntry *
             j = first_block_end(g, i, cfgs[k]);
             cand.push_back({i, j, k});
             feat.resize(feat.size() + kPlanFeatures);
-            pass_features(g, i, j, cfgs[k], feat.data() + feat.size() - kPlanFeatures);
+            // a candidate the planner runs as a dense block is priced as one
+            if (const uint64_t blk = range_dense_block(g, {i, j}, cfgs[k]))
+                dense_features(g, i, j, blk, cfgs[1], feat.data() + feat.size() - kPlanFeatures);
+            else
+                pass_features(g, i, j, cfgs[k], feat.data() + feat.size() - kPlanFeatures);
         }
     }
     std::vector<float> pred(cand.size());
@@ -746,6 +752,30 @@ qg_status learned_plan(const std::vector<Gate> &g0, int n, bool c64, PlanEntry *
         out->cfg.push_back(c.k);
         i = c.j;
     }
+    // The greedy width-5 plan priced by the same model: the learned plan replaces
+    // it only when predicted to be faster by more than kLearnedMargin, so that
+    // the model's error alone does not trade a greedy plan for a slower one.
+    {
+        constexpr double kLearnedMargin = 0.03;
+        std::vector<float> gf(sc.ranges.size() * kPlanFeatures);
+        for (size_t p = 0; p < sc.ranges.size(); ++p) {
+            const PassRange &r = sc.ranges[p];
+            float *f = gf.data() + p * kPlanFeatures;
+            if (const uint64_t blk = range_dense_block(g, r, cfgs[1]))
+                dense_features(g, r.g_begin, r.g_end, blk, cfgs[1], f);
+            else
+                pass_features(g, r.g_begin, r.g_end, cfgs[1], f);
+        }
+        std::vector<float> gp(sc.ranges.size());
+        st = sc.ranges.empty() ? QG_OK : qg_mlp_forward(g_cost_model, gf.data(), (int)gp.size(), gp.data());
+        if (st != QG_OK) return st;
+        double greedy_cost = 0.0;
+        for (float v : gp) greedy_cost += std::exp((double)v);
+        if (!(best[0] < (1.0 - kLearnedMargin) * greedy_cost)) {
+            out->ranges = sc.ranges;
+            out->cfg.assign(out->ranges.size(), 1);
+        }
+    }
     std::lock_guard<std::mutex> lk(g_plan_mu);
     if (g_plan_cache.size() >= kPlanCacheMax) g_plan_cache.clear();
     g_plan_cache[structure_hash(n, c64, g0)] = *out;
@@ -762,9 +792,9 @@ Program build_learned(const std::vector<Gate> &g0, const PlanEntry &e, int n, bo
                          candidate_config(n, c64, 1));
             continue;
         }
-        PlanConfig cfg = candidate_config(n, c64, e.cfg[p]);
-        std::vector<PassRange> one{e.ranges[p]};
-        append_program(&prog, build_program(g, one, cfg));
+        // the kernel choice of a greedy pass (special single-gate kernels, dense
+        // blocks from the break-even gate count) applies to learned passes too
+        append_range(&prog, g, e.ranges[p], candidate_config(n, c64, e.cfg[p]));
     }
     return prog;
 }

@@ -50,37 +50,30 @@ __device__ __forceinline__ uint64_t deposit(uint32_t v, const int8_t *q, int cnt
     return o;
 }
 
-template <typename R, int KB>
+template <typename R, int KB, int LB>
 __global__ void __launch_bounds__(256)
 k_dense(const DenseDesc D, const R *__restrict__ ut_re, const R *__restrict__ ut_im,
         typename Mfma<R>::C *__restrict__ psi) {
     using C = typename Mfma<R>::C;
     using Acc = typename Mfma<R>::Acc;
     constexpr int ROWS = 1 << KB;
-    constexpr int NBI = ROWS / 16;       // 16-row stripes of U (and of Y)
-    constexpr int WPI = 4 / NBI;         // waves per stripe
-    constexpr int KS = ROWS / 4;         // k-steps of 4
-    constexpr int kMaxJ = 8;             // column blocks per wave
-    const int L = D.l;
-    const int COLS = 1 << L;
+    constexpr int COLS = 1 << LB;
+    constexpr int NBI = ROWS / 16;                // 16-row stripes of U (and of Y)
+    constexpr int WPI = 4 / NBI;                  // waves per stripe
+    constexpr int KS = ROWS / 4;                  // k-steps of 4
+    constexpr int NBJ = COLS / 16;                // 16-column blocks of X (and of Y)
+    constexpr int JPW = (NBJ + WPI - 1) / WPI;    // column blocks per wave
+    constexpr int CSTEP = COLS < 256 ? COLS : 256;
+    constexpr int RSTEP = 256 / CSTEP;            // <= 16 <= ROWS
+    constexpr int NCOL = COLS / CSTEP;            // columns per thread
+    constexpr int NROW = ROWS / RSTEP;            // rows per thread and column
     extern __shared__ __align__(16) unsigned char smem[];
-    C *X = reinterpret_cast<C *>(smem);  // [ROWS][COLS]
+    C *X = reinterpret_cast<C *>(smem);           // [ROWS][COLS]
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int I = wave % NBI;            // this wave's stripe
-    const int j0 = wave / NBI;           // its column blocks: j0, j0 + WPI, ...
-
-    // The stripe's A fragments for every k-step, read once per tile (U is
-    // shared by all tiles and stays in the caches): A[i][k] = U[16 I + i][s + k]
-    // = UT[s + k][16 I + i], lane (li, lk) holding i = li, k = lk.
-    R ar[KS], ai[KS];
-#pragma unroll
-    for (int q = 0; q < KS; ++q) {
-        const int ka = 4 * q + lk;
-        ar[q] = ut_re[ka * ROWS + 16 * I + li];
-        ai[q] = ut_im[ka * ROWS + 16 * I + li];
-    }
+    const int I = wave % NBI;                     // this wave's stripe
+    const int j0 = wave / NBI;                    // its column blocks: j0, j0 + WPI, ...
 
     // Tile base: deposit the block index into the free runs.
     uint64_t gbase = 0;
@@ -93,44 +86,52 @@ k_dense(const DenseDesc D, const R *__restrict__ ut_re, const R *__restrict__ ut
         }
     }
     // Global offsets of the block-qubit patterns (rows), once per tile, in LDS
-    // after the tile.  A thread covers columns c0, c0 + cstep, ... and in each
-    // the rows r0, r0 + rstep, ...; loads go out in groups of 8 before their
-    // stores to LDS, so that each thread keeps several in flight.
-    uint64_t *rowoff = reinterpret_cast<uint64_t *>(X + (ROWS << L));
+    // after the tile.  A thread covers columns c0 + m CSTEP and in each the rows
+    // r0 + q RSTEP; all of its loads are issued before the first store to LDS.
+    uint64_t *rowoff = reinterpret_cast<uint64_t *>(X + ROWS * COLS);
     if (tid < ROWS) rowoff[tid] = deposit(tid, D.blk_q, KB);
-    const int cstep = COLS < 256 ? COLS : 256;
-    const int rstep = 256 / cstep;  // <= 16 <= ROWS
-    const int c0 = tid % cstep;
-    const int r0 = tid / cstep;
-    const int nrow = ROWS / rstep;
+    const int c0 = tid % CSTEP;
+    const int r0 = tid / CSTEP;
+    uint64_t cg[NCOL];
+#pragma unroll
+    for (int m = 0; m < NCOL; ++m) cg[m] = gbase | deposit(c0 + m * CSTEP, D.low_q, LB);
     __syncthreads();
-    for (int c = c0; c < COLS; c += cstep) {
-        const uint64_t cg = gbase | deposit(c, D.low_q, L);
-        int q0 = 0;
-        for (; q0 + 8 <= nrow; q0 += 8) {
-            C v[8];
+    {
+        C v[NCOL][NROW];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = psi[cg | rowoff[r0 + (q0 + q) * rstep]];
+        for (int m = 0; m < NCOL; ++m)
 #pragma unroll
-            for (int q = 0; q < 8; ++q) X[(r0 + (q0 + q) * rstep) * COLS + c] = v[q];
-        }
-        for (; q0 < nrow; ++q0) X[(r0 + q0 * rstep) * COLS + c] = psi[cg | rowoff[r0 + q0 * rstep]];
+            for (int q = 0; q < NROW; ++q) v[m][q] = psi[cg[m] | rowoff[r0 + q * RSTEP]];
+#pragma unroll
+        for (int m = 0; m < NCOL; ++m)
+#pragma unroll
+            for (int q = 0; q < NROW; ++q) X[(r0 + q * RSTEP) * COLS + c0 + m * CSTEP] = v[m][q];
+    }
+
+    // The stripe's A fragments for every k-step (U is shared by all tiles and
+    // stays in the caches): A[i][k] = U[16 I + i][s + k] = UT[s + k][16 I + i],
+    // lane (li, lk) holding i = li, k = lk.
+    R ar[KS], ai[KS];
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+        const int ka = 4 * q + lk;
+        ar[q] = ut_re[ka * ROWS + 16 * I + li];
+        ai[q] = ut_im[ka * ROWS + 16 * I + li];
     }
     __syncthreads();
 
     // Y[16 I .. 16 I + 15][16 J ..] for this wave's column blocks J; for complex
     // numbers Yr = Ur Xr + (-Ui) Xi and Yi = Ur Xi + Ui Xr.
-    const int nbj = COLS / 16;
-    Acc accr[kMaxJ], acci[kMaxJ];
+    Acc accr[JPW], acci[JPW];
 #pragma unroll
-    for (int q = 0; q < kMaxJ; ++q) {
+    for (int q = 0; q < JPW; ++q) {
         const int J = j0 + WPI * q;
-        if (J < nbj) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                accr[q][r] = (R)0;
-                acci[q][r] = (R)0;
-            }
+        for (int r = 0; r < 4; ++r) {
+            accr[q][r] = (R)0;
+            acci[q][r] = (R)0;
+        }
+        if (J < NBJ) {
 #pragma unroll
             for (int t = 0; t < KS; ++t) {
                 const C b = X[(4 * t + lk) * COLS + 16 * J + li];
@@ -144,9 +145,9 @@ k_dense(const DenseDesc D, const R *__restrict__ ut_re, const R *__restrict__ ut
     __syncthreads();
     // D fragment: lane holds rows 16 I + row(lane / 16, r), column 16 J + lane % 16.
 #pragma unroll
-    for (int q = 0; q < kMaxJ; ++q) {
+    for (int q = 0; q < JPW; ++q) {
         const int J = j0 + WPI * q;
-        if (J < nbj) {
+        if (J < NBJ) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 C y;
@@ -157,29 +158,54 @@ k_dense(const DenseDesc D, const R *__restrict__ ut_re, const R *__restrict__ ut
         }
     }
     __syncthreads();
-    for (int c = c0; c < COLS; c += cstep) {
-        const uint64_t cg = gbase | deposit(c, D.low_q, L);
-        for (int q0 = 0; q0 < nrow; ++q0) psi[cg | rowoff[r0 + q0 * rstep]] = X[(r0 + q0 * rstep) * COLS + c];
+    {
+        C v[NCOL][NROW];
+#pragma unroll
+        for (int m = 0; m < NCOL; ++m)
+#pragma unroll
+            for (int q = 0; q < NROW; ++q) v[m][q] = X[(r0 + q * RSTEP) * COLS + c0 + m * CSTEP];
+#pragma unroll
+        for (int m = 0; m < NCOL; ++m)
+#pragma unroll
+            for (int q = 0; q < NROW; ++q) psi[cg[m] | rowoff[r0 + q * RSTEP]] = v[m][q];
     }
 }
 
-template <typename R, int KB>
-hipError_t launch_k(const DenseDesc &D, const void *ut_re, const void *ut_im, void *psi, hipStream_t st) {
+template <typename R, int KB, int LB>
+hipError_t launch_kl(const DenseDesc &D, const void *ut_re, const void *ut_im, void *psi, hipStream_t st) {
     using C = typename Mfma<R>::C;
     // the tile, then the 2^k row offsets (uint64)
-    const size_t lds = (size_t(1) << (KB + D.l)) * sizeof(C) + (size_t(8) << KB);
+    const size_t lds = (size_t(1) << (KB + LB)) * sizeof(C) + (size_t(8) << KB);
     if (lds > 65536) {
         static bool done = false;
         if (!done) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_dense<R, KB>),
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_dense<R, KB, LB>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             if (e != hipSuccess) return e;
             done = true;
         }
     }
-    hipLaunchKernelGGL((k_dense<R, KB>), dim3((uint32_t)D.n_tiles), dim3(256), lds, st, D,
+    hipLaunchKernelGGL((k_dense<R, KB, LB>), dim3((uint32_t)D.n_tiles), dim3(256), lds, st, D,
                        static_cast<const R *>(ut_re), static_cast<const R *>(ut_im), static_cast<C *>(psi));
     return hipGetLastError();
+}
+
+// Tile widths: 2^L columns for L in 4 .. 13 - k.
+template <typename R, int KB>
+hipError_t launch_k(const DenseDesc &D, const void *ut_re, const void *ut_im, void *psi, hipStream_t st) {
+    switch (D.l) {
+    case 4: return launch_kl<R, KB, 4>(D, ut_re, ut_im, psi, st);
+    case 5: return launch_kl<R, KB, 5>(D, ut_re, ut_im, psi, st);
+    case 6: return launch_kl<R, KB, 6>(D, ut_re, ut_im, psi, st);
+    case 7: return launch_kl<R, KB, 7>(D, ut_re, ut_im, psi, st);
+    case 8:
+        if constexpr (KB + 8 <= 13) return launch_kl<R, KB, 8>(D, ut_re, ut_im, psi, st);
+        break;
+    case 9:
+        if constexpr (KB + 9 <= 13) return launch_kl<R, KB, 9>(D, ut_re, ut_im, psi, st);
+        break;
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace

@@ -155,6 +155,7 @@ const Knob kKnobs[] = {
     {"half_lds_c64", [](Tuning &t) { return &t.half_lds[1]; }, 0, 1},
     {"pipe_min_ops", [](Tuning &t) { return &t.pipe_min_ops; }, 1, 1 << 20},
     {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 0, 1 << 30},
+    {"dense_tile_bits", [](Tuning &t) { return &t.dense_tile_bits; }, 10, 13},
 };
 
 // A phase of a pass: the tile positions held in registers (slot order) and
@@ -1043,7 +1044,7 @@ void append_dense(Program *prog, const std::vector<Gate> &g, int begin, int end,
             D.blk_q[k++] = (int8_t)q;
         }
     D.k = k;
-    const int tile = std::min(n, cfg.tile_bits);
+    const int tile = std::min(n, tuning().dense_tile_bits);
     const int l = std::min(tile - k, n - k);
     int li = 0;
     uint64_t used = blk;
@@ -1088,76 +1089,85 @@ void append_dense(Program *prog, const std::vector<Gate> &g, int begin, int end,
     prog->passes.push_back(pd);
 }
 
+namespace {
+// Standalone SWAPs run as permutations: half the state when both qubits are at
+// or above the line bits, otherwise (lower qubit a lane bit) the whole state
+// with a cross-lane exchange.
+int swap_kind(const std::vector<Gate> &g, const PassRange &r, const PlanConfig &cfg) {
+    if (cfg.reverse || r.g_end - r.g_begin != 1 || g[r.g_begin].op != QG_SWAP) return 0;
+    const int line_bits = cfg.c64 ? 4 : 3;
+    const int lo = std::min(g[r.g_begin].q0, g[r.g_begin].q1);
+    if (lo >= line_bits) return PASS_SWAP2;
+    return cfg.n >= 12 && tuning().lane_swap ? PASS_SWAPL : 0;
+}
+
+// A single one-qubit mixing gate or CX whose target lies inside a cache line
+// runs as a cross-lane exchange with whole-line accesses.
+bool lane_gate(const std::vector<Gate> &g, const PassRange &r, const PlanConfig &cfg) {
+    if (cfg.reverse || r.g_end - r.g_begin != 1 || cfg.n < 12 || !tuning().lane_gate) return false;
+    const int line_bits = cfg.c64 ? 4 : 3;
+    const Gate &x = g[r.g_begin];
+    return ((is_one_qubit(x.op) && x.op != QG_RZ) || x.op == QG_CX) && x.q1 < line_bits;
+}
+}  // namespace
+
+uint64_t range_dense_block(const std::vector<Gate> &g, const PassRange &r, const PlanConfig &cfg) {
+    if (cfg.reverse || cfg.n < 8 || cfg.dense_min_gates >= (1 << 30)) return 0;
+    const uint64_t blk = dense_block_qubits(g, r.g_begin, r.g_end, cfg.n);
+    return blk && r.g_end - r.g_begin >= dense_threshold(cfg, popcount64(blk)) ? blk : 0;
+}
+
+void append_range(Program *prog, const std::vector<Gate> &g, const PassRange &r, const PlanConfig &cfg) {
+    const Gate &g1 = g[r.g_begin];
+    if (lane_gate(g, r, cfg)) {
+        std::vector<Item> its;
+        gate_items(g1, false, -1, &its);
+        DevOp op{};
+        op.kind = its[0].kind;
+        op.g = -1;
+        std::memcpy(op.m, its[0].m, sizeof op.m);
+        PassDesc pd{};
+        pd.flags = PASS_LANE1 | (tuning().xcd ? PASS_XCD : 0);
+        pd.run_start[0] = g1.q1;
+        pd.run_start[1] = g1.op == QG_CX ? g1.q0 : -1;
+        pd.n_tiles = 1ull << (cfg.n - 2);
+        pd.phase_begin = (int)prog->ops.size();
+        prog->ops.push_back(op);
+        prog->passes.push_back(pd);
+        return;
+    }
+    if (const int kind = swap_kind(g, r, cfg)) {
+        PassDesc pd{};
+        pd.flags = kind | (tuning().xcd ? PASS_XCD : 0);
+        pd.run_start[0] = g1.q0;
+        pd.run_start[1] = g1.q1;
+        pd.n_tiles = 1ull << (cfg.n - 2);
+        prog->passes.push_back(pd);
+        return;
+    }
+    if (const uint64_t blk = range_dense_block(g, r, cfg)) {
+        append_dense(prog, g, r.g_begin, r.g_end, blk, cfg);
+    } else {
+        std::vector<PassRange> one{r};
+        append_program(prog, build_program(g, one, cfg));
+    }
+}
+
 Program build_plan(const std::vector<Gate> &g0, const PlanConfig &cfg, std::vector<int> *order) {
     Schedule sc = schedule(g0, cfg);
     if (order) *order = sc.order;
     const std::vector<Gate> g = permute(g0, sc.order);
     const std::vector<PassRange> &ranges = sc.ranges;
-    const int line_bits = cfg.c64 ? 4 : 3;
-    // Standalone SWAPs run as permutations: half the state when both qubits are
-    // at or above the line bits, otherwise (lower qubit a lane bit) the whole
-    // state with a cross-lane exchange.
-    auto swap_kind = [&](const PassRange &r) -> int {
-        if (cfg.reverse || r.g_end - r.g_begin != 1 || g[r.g_begin].op != QG_SWAP) return 0;
-        const int lo = std::min(g[r.g_begin].q0, g[r.g_begin].q1);
-        if (lo >= line_bits) return PASS_SWAP2;
-        return cfg.n >= 12 && tuning().lane_swap ? PASS_SWAPL : 0;
-    };
-    // A single one-qubit mixing gate or CX whose target lies inside a cache line
-    // runs as a cross-lane exchange with whole-line accesses.
-    auto lane_gate = [&](const PassRange &r) {
-        if (cfg.reverse || r.g_end - r.g_begin != 1 || cfg.n < 12 || !tuning().lane_gate) return false;
-        const Gate &x = g[r.g_begin];
-        return ((is_one_qubit(x.op) && x.op != QG_RZ) || x.op == QG_CX) && x.q1 < line_bits;
-    };
     bool special = false;
-    for (const PassRange &r : ranges) special |= swap_kind(r) != 0 || lane_gate(r);
+    for (const PassRange &r : ranges) special |= swap_kind(g, r, cfg) != 0 || lane_gate(g, r, cfg);
     // Adjoint sweeps number their gradient rows across the whole program: one build.
     if (cfg.reverse || (!special && (cfg.dense_min_gates >= (1 << 30) || cfg.n < 8)))
         return build_program(g, ranges, cfg);
     Program prog;
     prog.pass_of_gate.assign(g.size(), -1);
     for (size_t p = 0; p < ranges.size(); ++p) {
-        const PassRange &r = ranges[p];
-        const Gate &g1 = g[r.g_begin];
-        if (lane_gate(r)) {
-            std::vector<Item> its;
-            gate_items(g1, false, -1, &its);
-            DevOp op{};
-            op.kind = its[0].kind;
-            op.g = -1;
-            std::memcpy(op.m, its[0].m, sizeof op.m);
-            PassDesc pd{};
-            pd.flags = PASS_LANE1 | (tuning().xcd ? PASS_XCD : 0);
-            pd.run_start[0] = g1.q1;
-            pd.run_start[1] = g1.op == QG_CX ? g1.q0 : -1;
-            pd.n_tiles = 1ull << (cfg.n - 2);
-            pd.phase_begin = (int)prog.ops.size();
-            prog.ops.push_back(op);
-            prog.passes.push_back(pd);
-            prog.pass_of_gate[r.g_begin] = (int)p;
-            continue;
-        }
-        if (const int kind = swap_kind(r)) {
-            PassDesc pd{};
-            pd.flags = kind | (tuning().xcd ? PASS_XCD : 0);
-            pd.run_start[0] = g1.q0;
-            pd.run_start[1] = g1.q1;
-            pd.n_tiles = 1ull << (cfg.n - 2);
-            prog.passes.push_back(pd);
-            prog.pass_of_gate[r.g_begin] = (int)p;
-            continue;
-        }
-        uint64_t blk = (!cfg.reverse && cfg.n >= 8 && cfg.dense_min_gates < (1 << 30))
-                           ? dense_block_qubits(g, r.g_begin, r.g_end, cfg.n) : 0;
-        if (blk && r.g_end - r.g_begin < dense_threshold(cfg, popcount64(blk))) blk = 0;
-        if (blk) {
-            append_dense(&prog, g, r.g_begin, r.g_end, blk, cfg);
-        } else {
-            std::vector<PassRange> one{r};
-            append_program(&prog, build_program(g, one, cfg));
-        }
-        for (int i = r.g_begin; i < r.g_end; ++i) prog.pass_of_gate[i] = (int)p;
+        append_range(&prog, g, ranges[p], cfg);
+        for (int i = ranges[p].g_begin; i < ranges[p].g_end; ++i) prog.pass_of_gate[i] = (int)p;
     }
     return prog;
 }

@@ -70,7 +70,8 @@ struct Tuning {
     // Gates from which a run on k = 4, 5, 6 qubits runs faster as one dense block
     // than as a tile pass, [c128, c64][k - 4] (measured on MI355X at 30 qubits
     // complex128 and 31 complex64, random gates of all ten kinds).
-    int dense_auto[2][3] = {{36, 36, 32}, {20, 20, 24}};
+    int dense_auto[2][3] = {{24, 20, 28}, {16, 16, 24}};
+    int dense_tile_bits = 11;  // a dense block's tile: its k qubits and the (this - k) lowest other qubits
     // Per pass class (see pass_class): tile bits, register bits and swizzle of
     // single-gate passes, and the swizzle of fused passes.  [dtype][class]
     int cls_tile[2][kPassClasses] = {{12, 12, 12, 10, 12}, {13, 13, 13, 11, 13}};
@@ -140,6 +141,13 @@ uint64_t touched_qubits(const Gate &g);
 // Dense step of gates [begin, end) on block qubits `blk` (4..6 qubits, covering
 // every touched qubit); appended to prog as a PASS_DENSE pass.
 void append_dense(Program *prog, const std::vector<Gate> &g, int begin, int end, uint64_t blk, const PlanConfig &cfg);
+// Block qubits of gates [r.g_begin, r.g_end) when the planner runs them as one
+// dense block (at most 6 qubits, at least the break-even gate count), else 0.
+uint64_t range_dense_block(const std::vector<Gate> &g, const PassRange &r, const PlanConfig &cfg);
+// One pass of gates [r.g_begin, r.g_end) in the kernel the planner picks for it:
+// the cross-lane gate or standalone SWAP kernels for those single gates, a dense
+// block at or above the break-even gate count, else a tile pass.
+void append_range(Program *prog, const std::vector<Gate> &g, const PassRange &r, const PlanConfig &cfg);
 // Block qubits for a dense step of gates [begin, end), or 0 if they touch more than 6 qubits.
 uint64_t dense_block_qubits(const std::vector<Gate> &g, int begin, int end, int n);
 // Gates a run on `k` block qubits (4..6, after padding) needs to run as a dense block.
