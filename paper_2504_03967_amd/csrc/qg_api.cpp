@@ -327,7 +327,43 @@ Program plan_batch_circuit(const qg_circuit &q, bool c64) {
     const std::vector<Gate> gl0 = load_gates(&w);
     Schedule sc = schedule(gl0, cfg);
     if (sc.ranges.empty()) sc.ranges.push_back({0, 0});  // identity pass keeps control flow uniform
-    return build_program(permute(gl0, sc.order), sc.ranges, cfg);
+    Program prog = build_program(permute(gl0, sc.order), sc.ranges, cfg);
+    // The state starts as |0...0>, and a pass mixes amplitudes only within its
+    // tiles, so before pass p an amplitude with a 1 on a qubit that no earlier
+    // pass held in its tile is still zero.  The first pass writes every tile;
+    // later passes skip the tiles where such a qubit is 1 (they hold zeros and
+    // stay zero), as if that qubit were a fixed bit with value 0.
+    if (w.n_qubits > cfg.tile_bits) {
+        const uint64_t all = w.n_qubits >= 64 ? ~0ull : (1ull << w.n_qubits) - 1;
+        uint64_t support = 0;
+        for (size_t p = 0; p < prog.passes.size(); ++p) {
+            PassDesc &pd = prog.passes[p];
+            uint64_t freeq = 0;
+            for (int r = 0; r < pd.n_runs; ++r) freeq |= ((1ull << pd.run_len[r]) - 1) << pd.run_start[r];
+            const uint64_t tileq = all & ~freeq & ~pd.fixed_mask;
+            const uint64_t zero = p > 0 ? freeq & ~support : 0;
+            support |= tileq;
+            if (!zero) continue;
+            pd.fixed_mask |= zero;  // fixed_val keeps these bits 0
+            pd.n_runs = 0;
+            int free_bits = 0;
+            for (int q = 0; q < w.n_qubits; ++q) {
+                if (!((freeq & ~zero) >> q & 1)) continue;
+                if (pd.n_runs > 0 && pd.run_start[pd.n_runs - 1] + pd.run_len[pd.n_runs - 1] == q) {
+                    pd.run_len[pd.n_runs - 1]++;
+                } else {
+                    pd.run_start[pd.n_runs] = q;
+                    pd.run_len[pd.n_runs] = 1;
+                    pd.n_runs++;
+                }
+                free_bits++;
+            }
+            pd.n_tiles = 1ull << free_bits;
+            pd.swz_bits = std::min(pd.swz_bits, free_bits / 2);
+            if (free_bits < 3) pd.flags &= ~PASS_XCD;
+        }
+    }
+    return prog;
 }
 
 struct BatchDev {

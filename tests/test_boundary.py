@@ -163,3 +163,28 @@ def test_plan_kernels_validates_and_reports_counts(qg):
     assert k[2] == -7 and set(k[:2]) <= set(range(len(qg.KERNEL_NAMES)))
     empty = W.Circuit(14, np.zeros((0, 3), np.int32), np.zeros((0, 3)), np.zeros(0, np.int32))
     assert qg.plan_kernels(empty) == []
+
+
+@pytest.mark.parametrize("dtype,amp,tile", [("c128", 16, 12), ("c64", 8, 13)])
+def test_batched_plan_bytes(qg, dtype, amp, tile):
+    """Batched form's byte count: a circuit that fits one tile moves nothing; a larger one
+    streams its state once per pass and the observable reads it once, except that a pass
+    skips the tiles where a qubit no earlier pass held is 1 (still zero from |0...0>)."""
+    small = W.CircuitBuilder(tile)
+    for q in range(tile):
+        small.g1(W.H, q)
+    assert qg.plan_bytes(small.build(), dtype, qg.FORM_BATCHED) == (1, 0.0)
+    n = 20
+    b = W.CircuitBuilder(n)
+    low = tile - 5                        # the batched tile: low block plus 5 high qubits
+    for q in range(low, low + 5):
+        b.g1(W.H, q)                      # pass 0: tile = qubits 0 .. tile-1
+    for q in range(low + 5, low + 10):
+        b.g1(W.H, q)                      # pass 1: 5 new high qubits
+    passes, hbm = qg.plan_bytes(b.build(), dtype, qg.FORM_BATCHED)
+    state = float(amp << n)
+    # pass 0 writes the state (no read), the observable reads it; pass 1 visits only the
+    # tiles whose free qubits above qubit low + 9 are 0: 2^(n - low - 10) of them
+    unseen = n - (low + 10)
+    assert passes == 2
+    assert hbm == 2 * state + 2 * state / (1 << unseen)
