@@ -309,6 +309,10 @@ qg_status qg_set_cost_model(qg_mlp *m);
  *                                    per precision and block width (24 / 20 / 28 gates
  *                                    for 4 / 5 / 6 qubits in complex128, 16 / 16 / 24
  *                                    in complex64); 1 << 30: never
+ *   adjoint_tile_bits / adjoint_low_bits
+ *                                    qg_adjoint_grad's reverse sweep in complex128: tile
+ *                                    qubits (8..11, default 10) and low block (3..8,
+ *                                    default 5); two states of 8 amplitudes per thread
  *   dense_tile_bits                  tile of a dense block: its k qubits and the
  *                                    (dense_tile_bits - k) lowest other qubits (10..13,
  *                                    default 11)

@@ -156,6 +156,8 @@ const Knob kKnobs[] = {
     {"pipe_min_ops", [](Tuning &t) { return &t.pipe_min_ops; }, 1, 1 << 20},
     {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 0, 1 << 30},
     {"dense_tile_bits", [](Tuning &t) { return &t.dense_tile_bits; }, 10, 13},
+    {"adjoint_tile_bits", [](Tuning &t) { return &t.adjoint_tile_bits; }, 8, 11},
+    {"adjoint_low_bits", [](Tuning &t) { return &t.adjoint_low_bits; }, 3, 8},
 };
 
 // A phase of a pass: the tile positions held in registers (slot order) and
@@ -438,13 +440,14 @@ PlanConfig default_config(int n, bool c64, int fusion) {
 void clamp_config(PlanConfig *c) {
     // Two complex128 states of 2^5 amplitudes per thread exceed the register
     // file, and with 2^4 the kernel runs one wave per SIMD: adjoint sweeps in
-    // complex128 take 2^11-amplitude tiles with 8 registers per thread and a
-    // 6-qubit low block (two waves per SIMD; the 24-qubit, 480-parameter
-    // gradient measured 37.5 -> 33.2 ms).
+    // complex128 take 8 registers per thread (two waves per SIMD), 2^10-amplitude
+    // tiles and a 5-qubit low block (the adjoint_* keys; the 24-qubit,
+    // 480-parameter gradient measured 37.5 ms with 2^12 tiles and 16 registers,
+    // 23.9 ms with 2^11 tiles and a 6-qubit low block, 23.1 ms now).
     if (c->reverse && !c->c64) {
-        c->tile_bits = std::min(c->tile_bits, 11);
+        c->tile_bits = std::min(c->tile_bits, tuning().adjoint_tile_bits);
         c->reg_bits = std::min(c->reg_bits, 3);
-        c->low_bits = std::min(c->low_bits, 6);
+        c->low_bits = std::min(c->low_bits, tuning().adjoint_low_bits);
     }
     c->low_bits = std::min(c->low_bits, c->tile_bits);
     c->max_high = std::max(1, std::min(c->max_high, c->tile_bits - c->low_bits));
