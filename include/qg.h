@@ -184,8 +184,9 @@ qg_status qg_adjoint_grad(const qg_circuit *c, qg_dtype dtype, const uint64_t *z
  * entries starting at 0).  Circuits whose state fits one tile (2^12 amplitudes
  * in complex128, 2^13 in complex64) run in one persistent launch and never
  * touch device memory; larger ones keep their states in device memory (at
- * most 32 GiB or half the free memory at a time, in groups) and run pass by
- * pass, one launch per pass index for all circuits of a group.  out: device
+ * most batch_group_mib MiB or half the free memory at a time, in groups) and
+ * run pass by pass, one launch per pass index for all circuits of a group.
+ * out: device
  * [n_circ] (written when the launch runs; each value is a fixed-order sum, the
  * same on every launch). */
 typedef enum { QG_OBS_ZZ_CHAIN = 0, QG_OBS_CSR = 1 } qg_obs_kind;
@@ -309,6 +310,9 @@ qg_status qg_set_cost_model(qg_mlp *m);
  *                                    per precision and block width (24 / 20 / 28 gates
  *                                    for 4 / 5 / 6 qubits in complex128, 16 / 16 / 24
  *                                    in complex64); 1 << 30: never
+ *   batch_group_mib                  batched form: at most this many MiB of multi-tile
+ *                                    circuit states at a time (and at most half the
+ *                                    free device memory; default 32768)
  *   adjoint_tile_bits / adjoint_low_bits
  *                                    qg_adjoint_grad's reverse sweep in complex128: tile
  *                                    qubits (8..11, default 10) and low block (3..8,

@@ -476,7 +476,7 @@ qg_status batch_build(qg_batch *b, const qg_circuit *circs, const int64_t *obs_o
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = size_t(8) << 30;
     const size_t largest = big.empty() ? 0 : (amp << bc[big[0]].n);
-    const size_t budget = std::max(largest, std::min(free_b / 2, size_t(32) << 30));
+    const size_t budget = std::max(largest, std::min(free_b / 2, size_t(tuning().batch_group_mib) << 20));
     std::vector<BatchItem> items;
     std::vector<BatchChunkItem> chunks;
     std::vector<int32_t> map;

@@ -156,6 +156,7 @@ const Knob kKnobs[] = {
     {"pipe_min_ops", [](Tuning &t) { return &t.pipe_min_ops; }, 1, 1 << 20},
     {"dense_min_gates", [](Tuning &t) { return &t.dense_min_gates; }, 0, 1 << 30},
     {"dense_tile_bits", [](Tuning &t) { return &t.dense_tile_bits; }, 10, 13},
+    {"batch_group_mib", [](Tuning &t) { return &t.batch_group_mib; }, 1, 1 << 20},
     {"adjoint_tile_bits", [](Tuning &t) { return &t.adjoint_tile_bits; }, 8, 11},
     {"adjoint_low_bits", [](Tuning &t) { return &t.adjoint_low_bits; }, 3, 8},
 };

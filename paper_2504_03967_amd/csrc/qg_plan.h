@@ -71,6 +71,7 @@ struct Tuning {
     // than as a tile pass, [c128, c64][k - 4] (measured on MI355X at 30 qubits
     // complex128 and 31 complex64, random gates of all ten kinds).
     int dense_auto[2][3] = {{24, 20, 28}, {16, 16, 24}};
+    int batch_group_mib = 32768;  // batched form: device states of multi-tile circuits per group (MiB)
     int adjoint_tile_bits = 10;  // reverse sweeps in complex128: tile qubits (two states in registers)
     int adjoint_low_bits = 5;    // and the low block of their passes
     int dense_tile_bits = 11;  // a dense block's tile: its k qubits and the (this - k) lowest other qubits

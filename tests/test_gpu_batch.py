@@ -68,6 +68,32 @@ def test_first_pass_skipping_tiles(qg, dtype):
     assert np.all(err <= TOL[dtype]), (int(np.argmax(err)), float(err.max()))
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_many_state_groups(qg, dtype):
+    """With a small state budget the multi-tile circuits run in many groups that reuse one
+    state buffer (each group: fill, passes, observable); results as with one group."""
+    lo = 13 if dtype == "c128" else 14
+    circs = W.config4(seed=8, n_circuits=24, n_min=lo - 3, n_max=18, l_min=1, l_max=4)
+    for n in (lo, lo + 2):  # first passes that skip tiles: states filled per group
+        b = W.CircuitBuilder(n)
+        b.g2(W.CP, n - 1, n - 2, 0.4)
+        b.g2(W.CX, n - 1, 0)
+        circs.append(b.build())
+    ref = oracle.batch_zz_chain(circs)
+    terms = np.array([max(c.n_qubits - 1, 1) for c in circs], dtype=np.float64)
+    one = qg.batch_expval(circs, dtype).cpu().numpy()
+    saved = qg.get_tuning("batch_group_mib")
+    try:
+        qg.set_tuning("batch_group_mib", 4)  # about one 18-qubit complex128 state per group
+        many = qg.batch_expval(circs, dtype).cpu().numpy()
+    finally:
+        qg.set_tuning("batch_group_mib", saved)
+    for out in (one, many):
+        err = np.abs(out - ref) / terms
+        assert np.all(err <= TOL[dtype]), (int(np.argmax(err)), float(err.max()))
+    assert np.array_equal(one, many)
+
+
 def test_graph_replays_and_new_params(qg):
     circs = W.config4(seed=21, n_circuits=40, n_min=8, n_max=18, l_min=2, l_max=5)
     stream = torch.cuda.Stream()
