@@ -57,6 +57,27 @@ def test_adjoint_matches_oracle_adjoint(qg, n, dtype):
     assert np.max(np.abs(grad.cpu().numpy() - rg)) < (1e-10 if dtype == "c128" else 1e-5 * w)
 
 
+@pytest.mark.parametrize("tile,low", [(8, 3), (9, 4), (11, 6)])
+def test_adjoint_reverse_tile_shapes(qg, tile, low):
+    """The reverse sweep's tile and low-block widths (tuning keys) change only the rounding:
+    every shape matches the oracle's adjoint at the complex128 tolerances."""
+    n = 15
+    circ, npar = mixed_trainable(n, 3, seed=170 + tile)
+    masks = W.zz_chain_masks(n)
+    coeffs = np.linspace(0.5, 1.5, masks.size)
+    rv, rg = oracle.adjoint_grad(circ, npar, masks, coeffs)
+    saved = {k: qg.get_tuning(k) for k in ("adjoint_tile_bits", "adjoint_low_bits")}
+    try:
+        qg.set_tuning("adjoint_tile_bits", tile)
+        qg.set_tuning("adjoint_low_bits", low)
+        val, grad = qg.adjoint_grad(circ, masks, coeffs, npar, "c128")
+    finally:
+        for k, v in saved.items():
+            qg.set_tuning(k, v)
+    assert abs(val.item() - rv) < 1e-12 * float(np.sum(coeffs))
+    assert np.max(np.abs(grad.cpu().numpy() - rg)) < 1e-10
+
+
 def test_config5_adjoint_vs_parameter_shift_and_fd(qg):
     circ = W.config5()
     n, npar = circ.n_qubits, circ.n_params

@@ -71,3 +71,31 @@ def test_dense_in_a_full_circuit(qg_dense):
     st.apply(circ, qg_dense.FUSE_GREEDY)
     torch.cuda.synchronize()
     assert np.max(np.abs(st.tensor.cpu().numpy() - oracle.simulate(circ))) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_dense_tile_widths_bitwise_equal(qg_dense, dtype):
+    """Every dense tile width (2^10 .. 2^13 amplitudes: the kernel's (k, L) instantiations for
+    k = 4, 5, 6) gives the same bits: each output sums the same k-steps in the same order;
+    the default width also matches the oracle."""
+    n = 16
+    saved = qg_dense.get_tuning("dense_tile_bits")
+    try:
+        for k in (4, 5, 6):
+            prep, circ = local_circuit(n, k, 40, seed=7 + k)
+            psi = oracle.apply(circ, oracle.simulate(prep))
+            ref = None
+            for tb in (10, 11, 12, 13):
+                qg_dense.set_tuning("dense_tile_bits", tb)
+                assert qg_dense.plan_kernels(circ, dtype, qg_dense.FUSE_GREEDY) == ["dense"]
+                st = qg_dense.State(n, dtype)
+                st.apply(prep, qg_dense.FUSE_NONE)
+                st.apply(circ, qg_dense.FUSE_GREEDY)
+                got = st.tensor.cpu().numpy()
+                st.close()
+                if ref is None:
+                    ref = got
+                    assert np.max(np.abs(got.astype(np.complex128) - psi)) < TOL[dtype]
+                assert np.array_equal(got, ref), (k, tb)
+    finally:
+        qg_dense.set_tuning("dense_tile_bits", saved)
