@@ -414,7 +414,7 @@ qg_status batch_build(qg_batch *b, const qg_circuit *circs, const int64_t *obs_o
     std::vector<PhaseDesc> phases;
     std::vector<DevOp> ops;
     std::vector<double> cost(nc);
-    std::vector<char> one_tile(nc, 0), needs_fill(nc, 0);
+    std::vector<char> one_tile(nc, 0), first_skips(nc, 0);
     int n_big = 0;
     const int tile_bits = batch_tile_bits(b->c64);
     const size_t amp = b->c64 ? 8 : 16;
@@ -446,8 +446,8 @@ qg_status batch_build(qg_batch *b, const qg_circuit *circs, const int64_t *obs_o
         if (!one_tile[c]) {
             if (q.n_qubits < tile_bits || prog.passes[0].b != tile_bits)
                 return fail(QG_EINTERNAL, "multi-tile batched circuit %d with %d-qubit tiles", c, prog.passes[0].b);
-            // a first pass that skips tiles leaves them unwritten: fill |0...0> first
-            needs_fill[c] = prog.passes[0].fixed_mask != 0;
+            // a first pass that skips tiles runs on the filled state like any pass
+            first_skips[c] = prog.passes[0].fixed_mask != 0;
             n_big = std::max(n_big, q.n_qubits);
         }
         cost[c] = (double)(1ull << q.n_qubits) * (1 + q.n_gates);
@@ -469,10 +469,7 @@ qg_status batch_build(qg_batch *b, const qg_circuit *circs, const int64_t *obs_o
     std::vector<int32_t> big;
     for (int c = 0; c < nc; ++c)
         if (!one_tile[c]) big.push_back(c);
-    std::stable_sort(big.begin(), big.end(), [&](int x, int y) {
-        if (bc[x].n != bc[y].n) return bc[x].n > bc[y].n;
-        return needs_fill[x] > needs_fill[y];
-    });
+    std::stable_sort(big.begin(), big.end(), [&](int x, int y) { return bc[x].n > bc[y].n; });
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = size_t(8) << 30;
     const size_t largest = big.empty() ? 0 : (amp << bc[big[0]].n);
@@ -514,17 +511,11 @@ qg_status batch_build(qg_batch *b, const qg_circuit *circs, const int64_t *obs_o
             bytes += sb;
         }
         state_bytes = std::max(state_bytes, bytes);
-        std::vector<int32_t> fill_c;
-        std::vector<uint64_t> fill_off;
         int max_pass = 0;
-        for (size_t k = 0; k < grp.size(); ++k) {
-            if (needs_fill[grp[k]]) {
-                fill_c.push_back(grp[k]);
-                fill_off.push_back(off[k]);
-            }
-            max_pass = std::max(max_pass, bc[grp[k]].n_pass);
-        }
-        add_chunk_step(BATCH_FILL, fill_c, fill_off);
+        for (size_t k = 0; k < grp.size(); ++k) max_pass = std::max(max_pass, bc[grp[k]].n_pass);
+        // every state starts as |0...0> (a plain fill at full occupancy); a first
+        // pass that visits every tile then only changes the tile holding index 0
+        add_chunk_step(BATCH_FILL, grp, off);
         for (int p = 0; p < max_pass; ++p) {
             BatchStep s{};
             s.kind = BATCH_PASS;
@@ -534,10 +525,12 @@ qg_status batch_build(qg_batch *b, const qg_circuit *circs, const int64_t *obs_o
                 if (p >= bc[c].n_pass) continue;
                 const int pi = bc[c].pass_begin + p;
                 const PassDesc &pd = passes[pi];
-                BatchItem it{s.blocks, off[k], pi, (p == 0 && !needs_fill[c]) ? 1 : 0};
-                map.insert(map.end(), pd.n_tiles, (int32_t)items.size());
+                const bool zero_init = p == 0 && !first_skips[c];
+                const uint64_t tiles = zero_init ? 1 : pd.n_tiles;  // tile 0 holds index 0
+                BatchItem it{s.blocks, off[k], pi, zero_init ? 1 : 0};
+                map.insert(map.end(), tiles, (int32_t)items.size());
                 items.push_back(it);
-                s.blocks += pd.n_tiles;
+                s.blocks += tiles;
                 const uint32_t l = pd.n_phase > 1 ? (uint32_t)((size_t(1) << pd.b) *
                                                                ((pd.flags & PASS_HALFX) ? amp / 2 : amp))
                                                   : 0u;
@@ -1054,12 +1047,19 @@ qg_status qg_plan_bytes(const qg_circuit *c, qg_dtype dtype, int form, int fusio
         Program prog = plan_batch_circuit(*c, c64);
         np = (int32_t)prog.passes.size();
         // A state of one tile stays in registers and LDS.  A larger one lives in
-        // device memory: its first pass starts from |0...0> in registers (no
-        // read; a first pass that skips tiles needs the state filled first),
-        // every pass streams it once, and the observable reads it once.
+        // device memory: it is filled with |0...0>, a first pass that visits
+        // every tile writes only the tile holding index 0 (from |0...0> in
+        // registers), every other pass streams the tiles it visits once, and the
+        // observable reads the state once.
         const bool one_tile = n <= batch_tile_bits(c64);
-        const bool fill = !one_tile && prog.passes[0].fixed_mask != 0;
-        bytes = one_tile ? 0.0 : program_hbm_bytes(prog, n, c64, 1) + (fill ? 2.0 * state : 0.0);
+        if (one_tile) {
+            bytes = 0.0;
+        } else {
+            const PassDesc &p0 = prog.passes[0];
+            const bool zero_init = p0.fixed_mask == 0;
+            bytes = 2.0 * state + program_hbm_bytes(prog, n, c64, 1) - pass_hbm_bytes(prog, p0, n, c64) +
+                    (zero_init ? std::ldexp(1.0, p0.b) * S : pass_hbm_bytes(prog, p0, n, c64));
+        }
     }
     if (n_passes) *n_passes = np;
     if (hbm_bytes) *hbm_bytes = bytes;

@@ -10,9 +10,10 @@
 // each launch applies the next pass of every circuit of a group that has one
 // left, one workgroup per (circuit, tile), so a launch has as many workgroups
 // as the group's states have tiles and streams like a pass over one large
-// state.  The first pass starts from |0...0> in registers (a state whose first
-// pass skips tiles is filled first); of its tiles only the one holding index 0
-// is not zero, so the others are stored as zeros without arithmetic.  The observable is reduced per chunk of
+// state.  Each state is filled with |0...0> first; from there a first pass
+// that visits every tile changes only the tile holding index 0 (its ops mix
+// amplitudes within tiles, and a zero tile stays zero), so it runs on that one
+// tile, starting from |0...0> in registers.  The observable is reduced per chunk of
 // kBatchChunk amplitudes, then per circuit in a fixed order.
 #include "qg_kernels.h"
 #include "qg_tile_dev.h"
@@ -101,25 +102,8 @@ k_batch_pass(const BatchItem *__restrict__ items, const int32_t *__restrict__ ma
     C *const st[2] = {states + it.state_off, nullptr};
     const bool active = tid < (1 << P.tb);
     C a[1][1 << RB];
-    if (it.zero_init) {
-        if (gbase != 0) {
-            // From |0...0> every tile but the one holding index 0 is zero, and the
-            // pass's ops (mixing within the tile, phases and controls read from
-            // index bits) map a zero tile to zero: store it without arithmetic.
-            if (active) {
-#pragma unroll
-                for (int e = 0; e < (1 << RB); ++e) {
-                    a[0][e].x = (R)0;
-                    a[0][e].y = (R)0;
-                }
-                tile_store<R, RB, 1>(P, ph[0], gbase, st, a, tid);
-            }
-            return;
-        }
-        tile_zero<R, RB>(P, ph[0], gbase, a, tid);
-    } else if (active) {
-        tile_load<R, RB, 1>(P, ph[0], gbase, st, a, tid);
-    }
+    if (it.zero_init) tile_zero<R, RB>(P, ph[0], gbase, a, tid);
+    else if (active) tile_load<R, RB, 1>(P, ph[0], gbase, st, a, tid);
     tile_phases<R, RB, 1>(P, ph, ops, DiagTables{nullptr, nullptr}, gbase, a, lds, nullptr, 0, t, tid, active);
     if (active) tile_store<R, RB, 1>(P, ph[P.n_phase - 1], gbase, st, a, tid);
 }

@@ -89,7 +89,8 @@ struct BatchItem {
     uint64_t begin;      // first workgroup of this (circuit, pass) in its launch
     uint64_t state_off;  // the circuit's state in the state buffer (amplitudes)
     int32_t pass;        // index into the batch's pass list
-    int32_t zero_init;   // 1: the state is |0...0> before this pass (no loads)
+    int32_t zero_init;   // 1: the state is |0...0> before this pass: the item is its
+                         // tile 0 alone, which starts from |0...0> in registers
 };
 // kBatchChunk amplitudes of a circuit's state: the unit of the fill and
 // observable kernels.

@@ -167,9 +167,10 @@ def test_plan_kernels_validates_and_reports_counts(qg):
 
 @pytest.mark.parametrize("dtype,amp,tile", [("c128", 16, 12), ("c64", 8, 13)])
 def test_batched_plan_bytes(qg, dtype, amp, tile):
-    """Batched form's byte count: a circuit that fits one tile moves nothing; a larger one
-    streams its state once per pass and the observable reads it once, except that a pass
-    skips the tiles where a qubit no earlier pass held is 1 (still zero from |0...0>)."""
+    """Batched form's byte count: a circuit that fits one tile moves nothing; a larger one is
+    filled with |0...0>, its first pass writes only the tile holding index 0, a later pass
+    skips the tiles where a qubit no earlier pass held is 1 (still zero), and the observable
+    reads the state once."""
     small = W.CircuitBuilder(tile)
     for q in range(tile):
         small.g1(W.H, q)
@@ -183,8 +184,9 @@ def test_batched_plan_bytes(qg, dtype, amp, tile):
         b.g1(W.H, q)                      # pass 1: 5 new high qubits
     passes, hbm = qg.plan_bytes(b.build(), dtype, qg.FORM_BATCHED)
     state = float(amp << n)
-    # pass 0 writes the state (no read), the observable reads it; pass 1 visits only the
-    # tiles whose free qubits above qubit low + 9 are 0: 2^(n - low - 10) of them
+    # the state is filled with |0...0> and read once by the observable; pass 0 writes its
+    # tile 0 only (the other tiles stay zero); pass 1 visits only the tiles whose free
+    # qubits above qubit low + 9 are 0: 2^(n - low - 10) of them
     unseen = n - (low + 10)
     assert passes == 2
-    assert hbm == 2 * state + 2 * state / (1 << unseen)
+    assert hbm == 2 * state + (amp << tile) + 2 * state / (1 << unseen)

@@ -45,8 +45,8 @@ def test_config4_every_circuit(qg):
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_first_pass_skipping_tiles(qg, dtype):
     """Multi-tile circuits whose first pass skips tiles (every op of it is conditioned on a
-    qubit outside the tile) start from a filled |0...0>, also in device memory that held
-    another batch's states just before."""
+    qubit outside the tile) run it on the filled |0...0> like any later pass, also in device
+    memory that held another batch's states just before."""
     lo = 13 if dtype == "c128" else 14
     amp = 16 if dtype == "c128" else 8
     junk = W.config4(seed=5, n_circuits=24, n_min=lo, n_max=17, l_min=2, l_max=3)
@@ -58,7 +58,7 @@ def test_first_pass_skipping_tiles(qg, dtype):
         b.g2(W.CP, n - 1, n - 2, 0.3 + k)
         b.g2(W.CX, n - 1, 0)
         circs.append(b.build())
-        # one pass over half the tiles (fixed control qubit), after a fill of the state
+        # a fill, one pass over half the tiles (fixed control qubit), the observable's read
         assert qg.plan_bytes(circs[-1], dtype, qg.FORM_BATCHED) == (1, 3.0 * (amp << n))
     circs += W.config4(seed=6, n_circuits=8, n_min=lo, n_max=lo + 3, l_min=1, l_max=3)
     out = qg.batch_expval(circs, dtype).cpu().numpy()
