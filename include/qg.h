@@ -240,9 +240,10 @@ qg_status qg_plan_kernels(const qg_circuit *c, qg_dtype dtype, int fusion_mode,
  * state of a SWAP or CX permutation pass, the tiles a pass conditioned on a
  * qubit outside its tile skips excluded).  form:
  *   QG_FORM_APPLY    qg_apply_circuit with fusion_mode;
- *   QG_FORM_ADJOINT  qg_adjoint_grad: the greedy forward sweep, the observable
- *                    (read psi twice, write lambda) and the reverse sweep over
- *                    both states (fusion_mode ignored);
+ *   QG_FORM_ADJOINT  qg_adjoint_grad: the greedy forward sweep (from the zeroed
+ *                    state, so its first passes skip the tiles still zero), the
+ *                    observable (read psi twice, write lambda) and the reverse
+ *                    sweep over both states (fusion_mode ignored);
  *   QG_FORM_BATCHED  one circuit of qg_batch_expval (fusion_mode ignored): 0 for
  *                    a circuit whose state fits one tile (registers and LDS
  *                    only), else its state in device memory streamed once per

@@ -317,6 +317,44 @@ PlanConfig batch_config(int n, bool c64) {
     return cfg;
 }
 
+// Passes of a program run on a state that holds |0...0> in device memory when
+// the program starts.  A pass mixes amplitudes only within its tiles (phases and
+// controls read index bits), so before pass p an amplitude with a 1 on a qubit
+// that no earlier pass held in its tile is still zero, and so is every tile
+// where such a free qubit is 1: passes from `first` on skip those tiles, as if
+// the qubit were a condition bit with value 0 (a pass visits at least one tile).
+void skip_zero_tiles(Program *prog, int n, size_t first) {
+    const uint64_t all = n >= 64 ? ~0ull : (1ull << n) - 1;
+    uint64_t support = 0;
+    for (size_t p = 0; p < prog->passes.size(); ++p) {
+        PassDesc &pd = prog->passes[p];
+        if (pd.flags & (PASS_DENSE | PASS_SWAP2 | PASS_SWAPL | PASS_LANE1)) return;  // tile passes only
+        uint64_t freeq = 0;
+        for (int r = 0; r < pd.n_runs; ++r) freeq |= ((1ull << pd.run_len[r]) - 1) << pd.run_start[r];
+        const uint64_t tileq = all & ~freeq & ~pd.fixed_mask;
+        const uint64_t zero = p >= first ? freeq & ~support : 0;
+        support |= tileq;
+        if (!zero) continue;
+        pd.fixed_mask |= zero;  // fixed_val keeps these bits 0
+        pd.n_runs = 0;
+        int free_bits = 0;
+        for (int q = 0; q < n; ++q) {
+            if (!((freeq & ~zero) >> q & 1)) continue;
+            if (pd.n_runs > 0 && pd.run_start[pd.n_runs - 1] + pd.run_len[pd.n_runs - 1] == q) {
+                pd.run_len[pd.n_runs - 1]++;
+            } else {
+                pd.run_start[pd.n_runs] = q;
+                pd.run_len[pd.n_runs] = 1;
+                pd.n_runs++;
+            }
+            free_bits++;
+        }
+        pd.n_tiles = 1ull << free_bits;
+        pd.swz_bits = std::min(pd.swz_bits, free_bits / 2);
+        if (free_bits < 3) pd.flags &= ~PASS_XCD;
+    }
+}
+
 // Plans one circuit of a batch.  Circuits narrower than the kernel's register
 // bits are planned on max(n, reg_bits) qubits; the extra qubits stay |0>.
 Program plan_batch_circuit(const qg_circuit &q, bool c64) {
@@ -328,41 +366,9 @@ Program plan_batch_circuit(const qg_circuit &q, bool c64) {
     Schedule sc = schedule(gl0, cfg);
     if (sc.ranges.empty()) sc.ranges.push_back({0, 0});  // identity pass keeps control flow uniform
     Program prog = build_program(permute(gl0, sc.order), sc.ranges, cfg);
-    // The state starts as |0...0>, and a pass mixes amplitudes only within its
-    // tiles, so before pass p an amplitude with a 1 on a qubit that no earlier
-    // pass held in its tile is still zero.  The first pass writes every tile;
-    // later passes skip the tiles where such a qubit is 1 (they hold zeros and
-    // stay zero), as if that qubit were a fixed bit with value 0.
-    if (w.n_qubits > cfg.tile_bits) {
-        const uint64_t all = w.n_qubits >= 64 ? ~0ull : (1ull << w.n_qubits) - 1;
-        uint64_t support = 0;
-        for (size_t p = 0; p < prog.passes.size(); ++p) {
-            PassDesc &pd = prog.passes[p];
-            uint64_t freeq = 0;
-            for (int r = 0; r < pd.n_runs; ++r) freeq |= ((1ull << pd.run_len[r]) - 1) << pd.run_start[r];
-            const uint64_t tileq = all & ~freeq & ~pd.fixed_mask;
-            const uint64_t zero = p > 0 ? freeq & ~support : 0;
-            support |= tileq;
-            if (!zero) continue;
-            pd.fixed_mask |= zero;  // fixed_val keeps these bits 0
-            pd.n_runs = 0;
-            int free_bits = 0;
-            for (int q = 0; q < w.n_qubits; ++q) {
-                if (!((freeq & ~zero) >> q & 1)) continue;
-                if (pd.n_runs > 0 && pd.run_start[pd.n_runs - 1] + pd.run_len[pd.n_runs - 1] == q) {
-                    pd.run_len[pd.n_runs - 1]++;
-                } else {
-                    pd.run_start[pd.n_runs] = q;
-                    pd.run_len[pd.n_runs] = 1;
-                    pd.n_runs++;
-                }
-                free_bits++;
-            }
-            pd.n_tiles = 1ull << free_bits;
-            pd.swz_bits = std::min(pd.swz_bits, free_bits / 2);
-            if (free_bits < 3) pd.flags &= ~PASS_XCD;
-        }
-    }
+    // The state starts as |0...0> (filled before the first pass runs); later
+    // passes skip what is still zero.
+    if (w.n_qubits > cfg.tile_bits) skip_zero_tiles(&prog, w.n_qubits, 1);
     return prog;
 }
 
@@ -1032,10 +1038,12 @@ qg_status qg_plan_bytes(const qg_circuit *c, qg_dtype dtype, int form, int fusio
         np = (int32_t)prog.passes.size();
         bytes = program_hbm_bytes(prog, n, c64, 1);
     } else if (form == QG_FORM_ADJOINT) {
-        // forward sweep (greedy), <O> and lambda = O psi (read psi twice, write
-        // lambda), then the reverse sweep over both states
+        // forward sweep (greedy, from the zeroed state: its first passes skip
+        // zero tiles), <O> and lambda = O psi (read psi twice, write lambda),
+        // then the reverse sweep over both states
         PlanConfig fcfg = plan_config(n, c64, QG_FUSE_GREEDY);
         Program fwd = build_plan(g, fcfg);
+        skip_zero_tiles(&fwd, n, 0);
         PlanConfig rcfg = fcfg;
         rcfg.reverse = true;
         clamp_config(&rcfg);
@@ -1201,6 +1209,7 @@ qg_status qg_adjoint_grad(const qg_circuit *c, qg_dtype dtype, const uint64_t *z
     HIP_TRY(launch_zero_state(c64, psi, dim, cx.stream), "state init");
     PlanConfig fcfg = plan_config(n, c64, QG_FUSE_GREEDY);
     Program fwd = build_plan(g, fcfg);
+    skip_zero_tiles(&fwd, n, 0);  // psi holds |0...0>: its first passes skip zero tiles
     st = run_program(cx, c64, fwd, psi, nullptr, nullptr);
     if (st != QG_OK) return st;
     // f and lambda = O psi
