@@ -112,6 +112,9 @@ def config3_timing(qg, W, torch, n: int = 31):
     e1.record(stream)
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) * 1e-3
+    # the same circuit through qg_apply_from_zero (reset included): passes skip the tiles
+    # that are still zero
+    t0 = event_time(stream, torch, lambda: st.apply_from_zero(circ, qg.FUSE_GREEDY))
     st.close()
     torch.cuda.empty_cache()
     flops = algorithmic_flops_per_index(circ, W) * (1 << n)
@@ -122,7 +125,8 @@ def config3_timing(qg, W, torch, n: int = 31):
             "fp64_TFLOPs": round(flops / t / 1e12, 2),
             "fp64_frac": round(flops / t / 1e12 / FP64_PEAK_TFLOPS, 4),
             "full_pass_equivalent_GBps": round(hbm / t / 1e9, 1),
-            "hbm_frac": round(hbm / t / 1e9 / HBM_PEAK_GBS, 4)}
+            "hbm_frac": round(hbm / t / 1e9 / HBM_PEAK_GBS, 4),
+            "t_from_zero_s": round(t0, 3)}
 
 
 def paper_shaped(qg, W, torch, n: int = 30):
@@ -141,8 +145,11 @@ def paper_shaped(qg, W, torch, n: int = 30):
         e1.record(stream)
         torch.cuda.synchronize()
         t = e0.elapsed_time(e1) * 1e-3
+        st.apply_from_zero(circ, qg.FUSE_GREEDY)
+        t0 = event_time(stream, torch, lambda: st.apply_from_zero(circ, qg.FUSE_GREEDY))
         out[name] = {"gates": circ.n_gates, "passes": npass, "t_ms": round(t * 1e3, 2),
-                     "amp_updates_per_s": circ.n_gates * (1 << n) / t}
+                     "amp_updates_per_s": circ.n_gates * (1 << n) / t,
+                     "t_from_zero_ms": round(t0 * 1e3, 2)}
     st.close()
     torch.cuda.empty_cache()
     return {"n_qubits": n, **out}
@@ -321,11 +328,13 @@ def cx_block_workloads(qg, W, torch, sizes, blocks_list, fusions, log, shots: in
                 t = event_time(stream, torch, lambda: st.apply(circ, fusion))
                 st.sample(100, 1)
                 ts = event_time(stream, torch, lambda: st.sample(shots, W.SEED_BASE + 71))
+                # the same through qg_apply_from_zero (reset included; zero tiles skipped)
+                t0 = event_time(stream, torch, lambda: st.apply_from_zero(circ, fusion))
                 key = f"{n}q_{dt}_{blocks}blocks_{fname}"
                 out[key] = {"gates": circ.n_gates, "passes": passes, "t_s": round(t, 4),
                             "amp_updates_per_s": circ.n_gates * (1 << n) / t,
                             "hbm_frac": round(hbm / t / 1e9 / HBM_PEAK_GBS, 4),
-                            "t_shots_ms": round(ts * 1e3, 3)}
+                            "t_shots_ms": round(ts * 1e3, 3), "t_from_zero_s": round(t0, 4)}
                 log(f"{key}: {out[key]}")
         st.close()
         torch.cuda.empty_cache()

@@ -122,6 +122,17 @@ qg_status qg_state_info(const qg_state *s, void **dev_ptr, int *n_qubits, qg_dty
  * code, non-finite parameter, n mismatch), QG_ENOMEM, QG_EDEVICE. */
 qg_status qg_apply_circuit(qg_state *s, const qg_circuit *c, int fusion_mode);
 
+/* Reset the state to |0...0> and apply the circuit (the paper's circuits all
+ * start from |0...0>): the same result as qg_state_reset followed by
+ * qg_apply_circuit, bit for bit.  Because the library wrote |0...0> itself, it
+ * knows which amplitudes are still zero when each pass starts: a pass mixes
+ * amplitudes only within its tiles, so an amplitude with a 1 on a qubit that no
+ * earlier pass held in its tile is zero, and each tile pass visits only the
+ * tiles that can hold a nonzero amplitude (up to the first pass that runs on
+ * another kernel, after which every pass visits all of its tiles).  Arguments
+ * and errors as for qg_apply_circuit. */
+qg_status qg_apply_from_zero(qg_state *s, const qg_circuit *c, int fusion_mode);
+
 /* Probabilities p_i = |alpha_i|^2 (eq. (hilbert)), computed in FP64 for both
  * dtypes.  idx == NULL: all 2^n values into out[2^n]; otherwise n_idx host
  * indices (each < 2^n) and out[n_idx].  out is a device pointer. */
@@ -240,6 +251,8 @@ qg_status qg_plan_kernels(const qg_circuit *c, qg_dtype dtype, int fusion_mode,
  * state of a SWAP or CX permutation pass, the tiles a pass conditioned on a
  * qubit outside its tile skips excluded).  form:
  *   QG_FORM_APPLY    qg_apply_circuit with fusion_mode;
+ *   QG_FORM_FROM_ZERO qg_apply_from_zero with fusion_mode: the reset's write of
+ *                    the state, then the passes over the tiles they visit;
  *   QG_FORM_ADJOINT  qg_adjoint_grad: the greedy forward sweep (from the zeroed
  *                    state, so its first passes skip the tiles still zero), the
  *                    observable (read psi twice, write lambda) and the reverse
@@ -252,7 +265,7 @@ qg_status qg_plan_kernels(const qg_circuit *c, qg_dtype dtype, int fusion_mode,
  *                    read once by the observable (n_qubits <= 22).
  * Either output may be NULL.  Errors: QG_EINVAL for an invalid circuit, dtype,
  * form or fusion mode. */
-typedef enum { QG_FORM_APPLY = 0, QG_FORM_ADJOINT = 1, QG_FORM_BATCHED = 2 } qg_form;
+typedef enum { QG_FORM_APPLY = 0, QG_FORM_ADJOINT = 1, QG_FORM_BATCHED = 2, QG_FORM_FROM_ZERO = 3 } qg_form;
 qg_status qg_plan_bytes(const qg_circuit *c, qg_dtype dtype, int form, int fusion_mode, int32_t *n_passes,
                         double *hbm_bytes);
 

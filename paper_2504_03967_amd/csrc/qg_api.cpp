@@ -1010,14 +1010,47 @@ double program_hbm_bytes(const Program &prog, int n, bool c64, int states) {
 
 }  // namespace
 
+namespace {
+// The plan qg_apply_circuit runs for `g` with fusion_mode.
+qg_status apply_plan(const std::vector<Gate> &g, int n, bool c64, int fusion_mode, Program *prog) {
+    if (fusion_mode == QG_FUSE_LEARNED) {
+        PlanEntry e;
+        qg_status st = learned_plan(g, n, c64, &e);
+        if (st != QG_OK) return st;
+        *prog = build_learned(g, e, n, c64);
+    } else {
+        *prog = build_plan(g, plan_config(n, c64, fusion_mode));
+    }
+    return QG_OK;
+}
+
+qg_status apply_checked(qg_state *s, const qg_circuit *c, int fusion_mode, bool from_zero) {
+    if (!s) return fail(QG_EINVAL, "state is NULL");
+    std::string err;
+    if (validate_circuit(c, -1, &err) != QG_OK) return fail(QG_EINVAL, "%s", err.c_str());
+    if (c->n_qubits != s->n)
+        return fail(QG_EINVAL, "circuit has %d qubits, state has %d", c->n_qubits, s->n);
+    if (fusion_mode < QG_FUSE_NONE || fusion_mode > QG_FUSE_LEARNED)
+        return fail(QG_EINVAL, "unknown fusion mode %d", fusion_mode);
+    if (from_zero) HIP_TRY(launch_zero_state(s->c64(), s->buf, s->dim(), s->cx.stream), "state init");
+    if (c->n_gates == 0) return QG_OK;
+    std::vector<Gate> g = load_gates(c);
+    Program prog;
+    qg_status st = apply_plan(g, s->n, s->c64(), fusion_mode, &prog);
+    if (st != QG_OK) return st;
+    if (from_zero) skip_zero_tiles(&prog, s->n, 0);
+    return run_program(s->cx, s->c64(), prog, s->buf, nullptr, nullptr);
+}
+}  // namespace
+
 qg_status qg_plan_bytes(const qg_circuit *c, qg_dtype dtype, int form, int fusion_mode, int32_t *n_passes,
                         double *hbm_bytes) {
     std::string err;
     if (validate_circuit(c, -1, &err) != QG_OK)
         return fail(QG_EINVAL, "%s", err.c_str());
     if (dtype != QG_C64 && dtype != QG_C128) return fail(QG_EINVAL, "unknown dtype %d", (int)dtype);
-    if (form < QG_FORM_APPLY || form > QG_FORM_BATCHED) return fail(QG_EINVAL, "unknown form %d", form);
-    if (form == QG_FORM_APPLY && (fusion_mode < QG_FUSE_NONE || fusion_mode > QG_FUSE_LEARNED))
+    if (form < QG_FORM_APPLY || form > QG_FORM_FROM_ZERO) return fail(QG_EINVAL, "unknown form %d", form);
+    if ((form == QG_FORM_APPLY || form == QG_FORM_FROM_ZERO) && (fusion_mode < QG_FUSE_NONE || fusion_mode > QG_FUSE_LEARNED))
         return fail(QG_EINVAL, "unknown fusion mode %d", fusion_mode);
     const bool c64 = dtype == QG_C64;
     const int n = c->n_qubits;
@@ -1025,18 +1058,14 @@ qg_status qg_plan_bytes(const qg_circuit *c, qg_dtype dtype, int form, int fusio
     std::vector<Gate> g = load_gates(c);
     int32_t np = 0;
     double bytes = 0.0;
-    if (form == QG_FORM_APPLY) {
+    if (form == QG_FORM_APPLY || form == QG_FORM_FROM_ZERO) {
         Program prog;
-        if (fusion_mode == QG_FUSE_LEARNED) {
-            PlanEntry e;
-            qg_status st = learned_plan(g, n, c64, &e);
-            if (st != QG_OK) return st;
-            prog = build_learned(g, e, n, c64);
-        } else {
-            prog = build_plan(g, plan_config(n, c64, fusion_mode));
-        }
+        qg_status st = g.empty() ? QG_OK : apply_plan(g, n, c64, fusion_mode, &prog);
+        if (st != QG_OK) return st;
+        if (form == QG_FORM_FROM_ZERO) skip_zero_tiles(&prog, n, 0);
         np = (int32_t)prog.passes.size();
-        bytes = program_hbm_bytes(prog, n, c64, 1);
+        // the reset writes the state once
+        bytes = program_hbm_bytes(prog, n, c64, 1) + (form == QG_FORM_FROM_ZERO ? state : 0.0);
     } else if (form == QG_FORM_ADJOINT) {
         // forward sweep (greedy, from the zeroed state: its first passes skip
         // zero tiles), <O> and lambda = O psi (read psi twice, write lambda),
@@ -1074,27 +1103,13 @@ qg_status qg_plan_bytes(const qg_circuit *c, qg_dtype dtype, int form, int fusio
     return QG_OK;
 }
 
+
 qg_status qg_apply_circuit(qg_state *s, const qg_circuit *c, int fusion_mode) {
-    if (!s) return fail(QG_EINVAL, "state is NULL");
-    std::string err;
-    if (validate_circuit(c, -1, &err) != QG_OK) return fail(QG_EINVAL, "%s", err.c_str());
-    if (c->n_qubits != s->n)
-        return fail(QG_EINVAL, "circuit has %d qubits, state has %d", c->n_qubits, s->n);
-    if (fusion_mode < QG_FUSE_NONE || fusion_mode > QG_FUSE_LEARNED)
-        return fail(QG_EINVAL, "unknown fusion mode %d", fusion_mode);
-    if (c->n_gates == 0) return QG_OK;
-    std::vector<Gate> g = load_gates(c);
-    Program prog;
-    if (fusion_mode == QG_FUSE_LEARNED) {
-        PlanEntry e;
-        qg_status st = learned_plan(g, s->n, s->c64(), &e);
-        if (st != QG_OK) return st;
-        prog = build_learned(g, e, s->n, s->c64());
-    } else {
-        PlanConfig cfg = plan_config(s->n, s->c64(), fusion_mode);
-        prog = build_plan(g, cfg);
-    }
-    return run_program(s->cx, s->c64(), prog, s->buf, nullptr, nullptr);
+    return apply_checked(s, c, fusion_mode, false);
+}
+
+qg_status qg_apply_from_zero(qg_state *s, const qg_circuit *c, int fusion_mode) {
+    return apply_checked(s, c, fusion_mode, true);
 }
 
 qg_status qg_probs(qg_state *s, const uint64_t *idx, int64_t n_idx, double *out) {

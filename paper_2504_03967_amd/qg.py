@@ -23,7 +23,7 @@ OBS_ZZ_CHAIN, OBS_CSR = 0, 1
 
 EXPORTS = (
     "qg_state_alloc", "qg_state_free", "qg_state_reset", "qg_state_set_stream", "qg_state_info",
-    "qg_apply_circuit", "qg_probs", "qg_sample", "qg_expval", "qg_adjoint_grad", "qg_batch_expval",
+    "qg_apply_circuit", "qg_apply_from_zero", "qg_probs", "qg_sample", "qg_expval", "qg_adjoint_grad", "qg_batch_expval",
     "qg_plan_passes", "qg_plan_kernels", "qg_last_error", "qg_version", "qg_set_tuning", "qg_get_tuning",
     "qg_batch_create", "qg_batch_set_params", "qg_batch_launch", "qg_batch_free",
     "qg_mlp_create", "qg_mlp_n_params", "qg_mlp_set_params", "qg_mlp_get_params", "qg_mlp_forward",
@@ -60,6 +60,7 @@ def _load() -> ctypes.CDLL:
         "qg_state_set_stream": [P, P],
         "qg_state_info": [P, P, P, P],
         "qg_apply_circuit": [P, P, ctypes.c_int],
+        "qg_apply_from_zero": [P, P, ctypes.c_int],
         "qg_probs": [P, P, I64, P],
         "qg_sample": [P, I64, U64, P],
         "qg_expval": [P, P, P, ctypes.c_int, P, P],
@@ -193,6 +194,12 @@ class State:
     def apply(self, circ, fusion: int = FUSE_GREEDY) -> "State":
         ca = CircuitArgs(circ)
         _check(lib.qg_apply_circuit(self.handle, ca.ptr, int(fusion)))
+        return self
+
+    def apply_from_zero(self, circ, fusion: int = FUSE_GREEDY) -> "State":
+        """Reset to |0...0> and apply circ (qg_apply_from_zero: passes skip tiles still zero)."""
+        ca = CircuitArgs(circ)
+        _check(lib.qg_apply_from_zero(self.handle, ca.ptr, int(fusion)))
         return self
 
     def probs(self, idx: Optional[Sequence[int]] = None) -> torch.Tensor:
@@ -410,12 +417,13 @@ def plan_passes(circ, dtype="c128", fusion: int = FUSE_GREEDY):
     return pog[:ca.gt.shape[0]], int(npass.value)
 
 
-FORM_APPLY, FORM_ADJOINT, FORM_BATCHED = 0, 1, 2
+FORM_APPLY, FORM_ADJOINT, FORM_BATCHED, FORM_FROM_ZERO = 0, 1, 2, 3
 
 
 def plan_bytes(circ, dtype="c128", form: int = FORM_APPLY, fusion: int = FUSE_GREEDY):
     """(passes, HBM bytes the plan moves) of qg_apply_circuit (form FORM_APPLY, with
-    `fusion`), qg_adjoint_grad (FORM_ADJOINT) or one batched circuit (FORM_BATCHED)."""
+    `fusion`), qg_apply_from_zero (FORM_FROM_ZERO, with `fusion`), qg_adjoint_grad
+    (FORM_ADJOINT) or one batched circuit (FORM_BATCHED)."""
     ca = CircuitArgs(circ)
     npass = ctypes.c_int32()
     b = ctypes.c_double()

@@ -190,3 +190,20 @@ def test_batched_plan_bytes(qg, dtype, amp, tile):
     unseen = n - (low + 10)
     assert passes == 2
     assert hbm == 2 * state + (amp << tile) + 2 * state / (1 << unseen)
+
+
+def test_from_zero_plan_bytes(qg):
+    """qg_apply_from_zero's byte count: the reset writes the state; the first pass visits only
+    tile 0 (every other tile is zero); the second visits the tiles whose free qubits outside
+    the first pass's tile are 0."""
+    n = 20
+    b = W.CircuitBuilder(n)
+    for q in range(7, 17):
+        b.g1(W.H, q)                          # two greedy passes: high qubits 7..11, 12..16
+    circ = b.build()
+    state = float(16 << n)
+    passes, full = qg.plan_bytes(circ, "c128", qg.FORM_APPLY)
+    assert passes == 2 and full == 4 * state
+    passes, zero = qg.plan_bytes(circ, "c128", qg.FORM_FROM_ZERO)
+    assert passes == 2
+    assert zero == state + 2 * (16 << 12) + 2 * state / 8

@@ -467,3 +467,56 @@ def test_large_shot_counts(qg):
     counts = np.bincount(idx.astype(np.int64), minlength=1 << n)
     assert chi_square_p(counts, np.abs(psi) ** 2, shots) > 0.01
     assert np.mean(idx[:10000] == oracle.sample(psi, 10000, 1234)) >= 0.999
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_apply_from_zero_equals_reset_and_apply(qg, dtype):
+    """qg_apply_from_zero passes visit only the tiles that can hold nonzero amplitudes; the
+    state equals qg_state_reset + qg_apply_circuit bit for bit, for both fusion modes, on
+    circuits whose passes run on the tile, lane-gate, SWAP and dense kernels; and it matches
+    the oracle."""
+    n = 20 if dtype == "c128" else 21
+    special = W.CircuitBuilder(n)
+    special.g2(W.SWAP, n - 1, n - 3)          # standalone SWAP first: nothing is skipped after it
+    special.g1(W.H, 0)
+    special = W.concat(special.build(), W.random_circuit(n, 40, seed=9))
+    lane = W.CircuitBuilder(n)
+    for q in range(6, n):
+        lane.g1(W.H, q)                       # tile passes first, then a lane-kernel gate
+    lane.g1(W.RY, 1, 0.3)
+    lane = W.concat(lane.build(), W.cx_blocks(n, 20, 4))
+    circs = [W.qft(n).build(), W.cx_blocks(n, 60, 3), W.config3(n, layers=3), special, lane]
+    a = qg.State(n, dtype)
+    b = qg.State(n, dtype)
+    junk = prep_layer(n, 5)
+    for k, c in enumerate(circs):
+        for fusion in (qg.FUSE_NONE, qg.FUSE_GREEDY):
+            a.reset()
+            a.apply(c, fusion)
+            b.apply(junk, qg.FUSE_GREEDY)     # any prior contents: the call resets first
+            b.apply_from_zero(c, fusion)
+            torch.cuda.synchronize()
+            assert torch.equal(a.tensor, b.tensor), (k, fusion)
+            if k == 1 and fusion == qg.FUSE_GREEDY:
+                assert np.max(np.abs(host(b) - oracle.simulate(c))) < TOL[dtype]
+    # a dense block among the passes
+    saved = qg.get_tuning("dense_min_gates")
+    try:
+        qg.set_tuning("dense_min_gates", 1)
+        db = W.CircuitBuilder(n)
+        for q in range(n):
+            db.g1(W.H, q)
+        for q in (0, 3, 7, 12):
+            db.g1(W.RY, q, 0.1 * q + 0.2)
+        for q in (0, 3, 7):
+            db.g2(W.CX, q, 12)
+        c = db.build()
+        a.reset()
+        a.apply(c, qg.FUSE_GREEDY)
+        b.apply_from_zero(c, qg.FUSE_GREEDY)
+        torch.cuda.synchronize()
+        assert torch.equal(a.tensor, b.tensor)
+    finally:
+        qg.set_tuning("dense_min_gates", saved)
+    a.close()
+    b.close()
