@@ -326,6 +326,7 @@ def cx_block_workloads(qg, W, torch, sizes, blocks_list, fusions, log, shots: in
                 passes, hbm = qg.plan_bytes(circ, dt, qg.FORM_APPLY, fusion)
                 st.reset()
                 t = event_time(stream, torch, lambda: st.apply(circ, fusion))
+                log(f"{n}q {dt} {blocks} blocks {fname}: apply {t:.4f} s")
                 st.sample(100, 1)
                 ts = event_time(stream, torch, lambda: st.sample(shots, W.SEED_BASE + 71))
                 # the same through qg_apply_from_zero (reset included; zero tiles skipped)
