@@ -48,11 +48,13 @@ constexpr int qref_global(int q) { return -1 - q; }
 // host), and each entry multiplies tf (entries [e_begin, s_begin[0])) or r_j
 // (entries [s_begin[j], s_begin[j+1])) by f1 where its condition holds, else
 // by f0.  The condition reads thread bits or qubits outside the tile only:
-// bit of ref a, and also of ref c when c != kNoRef.
+// every tile position in tmask (thread bits) and every qubit in gmask (outside
+// the tile, the same for the whole tile) is 1.
 constexpr int32_t kNoRef = 1 << 30;
 struct DiagEntry {
-    int32_t a, c;
-    int32_t pad[2];
+    uint32_t tmask;   // tile positions held by thread bits
+    uint32_t f0_one;  // 1: f0 is exactly 1, so a tile where gmask fails skips the entry
+    uint64_t gmask;   // qubits outside the tile
     double f0[2], f1[2];
 };
 struct DiagRun {

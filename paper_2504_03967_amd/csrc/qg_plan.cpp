@@ -701,8 +701,12 @@ void append_diag_run(const std::vector<Item> &items, const std::vector<int> &run
     std::vector<DiagEntry> thr, slot[kMaxRegBits];
     auto entry = [](int a, int c, cd f0, cd f1) {
         DiagEntry e{};
-        e.a = a;
-        e.c = c;
+        for (int ref : {a, c}) {
+            if (ref == kNoRef) continue;
+            if (ref >= 0) e.tmask |= 1u << ref;                  // tile position (a thread bit here)
+            else e.gmask |= 1ull << (-1 - ref);                 // qubit outside the tile
+        }
+        e.f0_one = f0 == cd(1.0) ? 1u : 0u;
         e.f0[0] = f0.real(), e.f0[1] = f0.imag();
         e.f1[0] = f1.real(), e.f1[1] = f1.imag();
         return e;

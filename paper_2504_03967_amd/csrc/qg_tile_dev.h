@@ -109,20 +109,22 @@ struct DiagTables {
     const DiagEntry *entries;
 };
 
-// Condition of a diagonal-run entry for this thread (refs are thread bits or
-// qubits outside the tile).
-__device__ __forceinline__ bool entry_on(const DiagEntry &x, uint64_t gbase, uint32_t tp) {
-    bool on = make_bit(x.a, gbase).of(tp);
-    if (x.c != kNoRef) on = on && make_bit(x.c, gbase).of(tp);
-    return on;
-}
-
-// (r, i) *= (on ? f1 : f0), in FP64.
-__device__ __forceinline__ void cmul_acc(double &r, double &i, bool on, const double (&f0)[2], const double (&f1)[2]) {
-    const double fr = on ? f1[0] : f0[0], fi = on ? f1[1] : f0[1];
-    const double nr = r * fr - i * fi;
-    i = r * fi + i * fr;
-    r = nr;
+// (r, i) *= the product of entries [begin, end) for this thread: f1 where the
+// entry's qubits are all 1, else f0.  The part of the condition on qubits
+// outside the tile is the same for the whole tile, and where it fails an entry
+// with f0 = 1 is skipped.
+__device__ __forceinline__ void entries_mul(const DiagEntry *__restrict__ es, int begin, int end, uint64_t gbase,
+                                            uint32_t tp, double &r, double &i) {
+    for (int k = begin; k < end; ++k) {
+        const DiagEntry &x = es[k];
+        const bool tile_on = (gbase & x.gmask) == x.gmask;
+        if (!tile_on && x.f0_one) continue;
+        const bool on = tile_on && (tp & x.tmask) == x.tmask;
+        const double fr = on ? x.f1[0] : x.f0[0], fi = on ? x.f1[1] : x.f0[1];
+        const double nr = r * fr - i * fi;
+        i = r * fi + i * fr;
+        r = nr;
+    }
 }
 
 // Component-wise select (a select of whole 16-byte vectors can become a select
@@ -490,19 +492,13 @@ __device__ __forceinline__ void apply_op(const DevOp &op, const DiagTables &dt, 
         // built in FP64 from the element without its top slot bit.
         const DiagRun &d = dt.runs[op.a];
         double tr = d.c0[0], ti = d.c0[1];
-        for (int k = d.e_begin; k < d.s_begin[0]; ++k) {
-            const DiagEntry &x = dt.entries[k];
-            cmul_acc(tr, ti, entry_on(x, gbase, tp), x.f0, x.f1);
-        }
+        entries_mul(dt.entries, d.e_begin, d.s_begin[0], gbase, tp, tr, ti);
         double rr[RB], ri[RB];
 #pragma unroll
         for (int j = 0; j < RB; ++j) {
             rr[j] = d.r[j][0];
             ri[j] = d.r[j][1];
-            for (int k = d.s_begin[j]; k < d.s_begin[j + 1]; ++k) {
-                const DiagEntry &x = dt.entries[k];
-                cmul_acc(rr[j], ri[j], entry_on(x, gbase, tp), x.f0, x.f1);
-            }
+            entries_mul(dt.entries, d.s_begin[j], d.s_begin[j + 1], gbase, tp, rr[j], ri[j]);
         }
         double fr[NR], fi[NR];
         fr[0] = tr;
