@@ -361,7 +361,8 @@ qg_status qg_set_cost_model(qg_mlp *m);
  *                                    inside a cache line runs as a cross-lane exchange
  *   half_lds_c128, half_lds_c64      1 / 0: multi-phase passes move the tile between
  *                                    layouts through LDS as real parts, then imaginary
- *                                    parts (half the LDS per workgroup)
+ *                                    parts (half the LDS per workgroup); the batched
+ *                                    form always does so
  * Errors: QG_EINVAL for an unknown key or a value out of range.  Not
  * thread-safe against concurrent planning. */
 qg_status qg_set_tuning(const char *key, int64_t value);

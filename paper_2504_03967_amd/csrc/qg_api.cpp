@@ -309,6 +309,10 @@ PlanConfig batch_config(int n, bool c64) {
     cfg.low_bits = c64 ? 8 : 7;
     cfg.max_high = 5;
     cfg.swz_bits = 0;
+    // Layout exchanges of half the tile (real parts, then imaginary parts): the
+    // pass kernels cap their registers at three workgroups per CU, which the
+    // LDS then also fits in both precisions.
+    cfg.half_lds = true;
     cfg.max_gates_per_pass = n <= cfg.tile_bits ? (1 << 30) : 4096;
     cfg.use_classes = false;  // the persistent kernel is built for one register width
     cfg.diag_run_min = 0;     // its programs carry no fused diagonal runs

@@ -78,10 +78,11 @@ k_batch(const BatchCirc *__restrict__ circs, const int32_t *__restrict__ order, 
 }
 
 // Register budget of the pass kernel: the complex128 form with 16 amplitudes
-// per thread fits three workgroups per CU, as the single-state tile pass does.
+// per thread and the complex64 form with 32 fit three workgroups per CU, as the
+// single-state tile pass does.
 template <typename R, int RB>
 struct BatchWaves {
-    static constexpr int value = (sizeof(R) == 8 && RB == 4) ? 3 : 1;
+    static constexpr int value = ((sizeof(R) == 8 && RB == 4) || (sizeof(R) == 4 && RB == 5)) ? 3 : 1;
 };
 
 // One pass of one circuit on one tile of its state.
