@@ -15,7 +15,9 @@ using namespace dev;
 
 // Occupancy floor for the compiler's register budget: the complex128 kernel
 // with 16 amplitudes per thread runs multi-phase passes with half-LDS
-// exchanges at three workgroups per CU when it fits 168 registers.
+// exchanges at three workgroups per CU when it fits 168 registers, and so does
+// the adjoint's two-state kernel with 8 amplitudes of each state per thread
+// (a few registers spill there; it is still faster than at two workgroups).
 template <typename R, int RB, int NS>
 struct TileWaves {
     static constexpr int value = (sizeof(R) == 8 && ((RB == 4 && NS == 1) || (RB == 3 && NS == 2))) ? 3 : 1;
