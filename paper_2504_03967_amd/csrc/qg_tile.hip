@@ -18,9 +18,13 @@ using namespace dev;
 // exchanges at three workgroups per CU when it fits 168 registers, and so does
 // the adjoint's two-state kernel with 8 amplitudes of each state per thread
 // (a few registers spill there; it is still faster than at two workgroups).
+// The complex64 kernel with 16 amplitudes per thread runs four workgroups per
+// CU in 128 registers (also with a small spill, and faster than three).
 template <typename R, int RB, int NS>
 struct TileWaves {
-    static constexpr int value = (sizeof(R) == 8 && ((RB == 4 && NS == 1) || (RB == 3 && NS == 2))) ? 3 : 1;
+    static constexpr int value = (sizeof(R) == 8 && ((RB == 4 && NS == 1) || (RB == 3 && NS == 2))) ? 3
+                                 : (sizeof(R) == 4 && RB == 4 && NS == 1)                            ? 4
+                                                                                                     : 1;
 };
 
 template <typename R, int RB, int NS>
